@@ -1,0 +1,263 @@
+"""Throughput of the batched macroscopic cross-section lookup on one MI355X.
+
+One step = one call of xs_lookup_batch over the whole batch (queue sort, when
+the parameters ask for it, plus the lookup kernel), inputs resident in HBM.
+The workload is the full-size synthetic table set: 355 nuclides x 11,303
+grid points, 12 materials of 4 to 321 nuclides, 10,000,000 lookups with
+log-uniform energies and uniform materials (see synth.workloads).
+
+Two forms are timed: the plain FP64 lookup (per-nuclide bisection, no sort,
+256-lane blocks, one lookup per lane) and the FP32 form with parameters
+chosen by the library's tuner; `value` is the latter.  The JSON line carries
+the dominant kernel's roofline (algorithmic bytes per lookup x lookups per
+launch / average kernel time from HIP events on the launch stream) and the
+serial CPU oracle's rate on a bounded sample of the same queries.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = ("macro-XS lookups/s (FP64 plain vs FP32 autotuned) + % HBM "
+          "roofline, 1 MI355X")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_lookup(precision: int, nbar: float) -> float:
+    """Algorithmic bytes one lookup must move.
+
+    FP64: energy + material in (12), five sums out (40), and per nuclide the
+    bracketing pair of points (2 x (8 energy + 5 x 8 channels) = 96) plus its
+    material entry (4 id + 8 density).  FP32 form: 12 in, 20 out, per nuclide
+    2 x (8 + 5 x 4) = 56 plus 8 (id + FP32 density)."""
+    if precision == 0:
+        return 52.0 + 108.0 * nbar
+    return 32.0 + 64.0 * nbar
+
+
+def lookup_sources_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2402_09222_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.startswith("xs_lookup") or f == "xs_internal.h":
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind: str, n: int):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "lookup_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kind)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != lookup_sources_hash():
+        return None
+    if rec.get("n_lookups") != n:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def time_steps(fn, steps: int, warmup: int):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def kernel_time(xs, h, fn, calls: int) -> dict:
+    import torch
+    torch.cuda.synchronize()
+    xs.xs_profile_begin(h)
+    for _ in range(calls):
+        fn()
+    prof = xs.xs_profile_end(h)
+    c = max(prof["calls"], 1)
+    return {"ms_lookup": prof["ms_lookup"] / c, "ms_sort": prof["ms_sort"] / c,
+            "ms_total": prof["ms_total"] / c, "calls": prof["calls"]}
+
+
+def cpu_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(tables, q, seconds: float) -> dict:
+    import oracle
+    ot = oracle.OracleTables(tables)
+    cores = cpu_cores()
+    probe = min(len(q), 4000)
+    t0 = time.perf_counter()
+    oracle.lookup(ot, q.E[:probe], q.mat[:probe])
+    rate1 = probe / max(time.perf_counter() - t0, 1e-9)
+    n = int(min(len(q), max(probe, rate1 * cores * seconds)))
+    t0 = time.perf_counter()
+    oracle.lookup(ot, q.E[:n], q.mat[:n], threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "lookups/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {n} of the {len(q)} lookups, serial oracle "
+                      f"(gcc -O2) on {cores} threads, each a contiguous slice; "
+                      f"{dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--bins", type=int, default=8192)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-union", action="store_true",
+                    help="skip the 5.7 GB unionized index table")
+    ap.add_argument("--params", type=str, default=None,
+                    help="JSON dict of FP32 params instead of tuning")
+    ap.add_argument("--only", choices=["plain", "tuned"], default=None,
+                    help="time one form only (for profiling runs)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not "
+              "supported by this single-GPU build", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_2402_09222_amd import xs
+
+    log("generating config-2 tables and queries")
+    t = synth.config2_tables()
+    q = synth.config2_queries(args.n)
+    nbar = synth.mean_nuclides(t, q)
+    flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH
+    if not args.no_union:
+        flags |= xs.XS_BUILD_UNIONIZED
+    t0 = time.perf_counter()
+    h = xs.xs_create_tables(t, flags, args.bins)
+    build_s = time.perf_counter() - t0
+    info = xs.xs_table_info(h)
+    log(f"tables built in {build_s:.2f} s; mean nuclides per lookup {nbar:.2f}")
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    n = len(q)
+
+    def runner(params):
+        out = torch.empty((n, 5), device="cuda:0",
+                          dtype=torch.float64 if params.precision == 0
+                          else torch.float32)
+        nb = xs.xs_workspace_size(h, n, params)
+        ws = xs._workspace(nb, E.device)
+
+        def fn():
+            xs.xs_lookup_batch(h, E, m, out=out, params=params, workspace=ws)
+        return fn
+
+    def measure(params, kind):
+        fn = runner(params)
+        sec = time_steps(fn, args.steps, args.warmup)
+        kt = kernel_time(xs, h, fn, max(args.steps, 3))
+        B = bytes_per_lookup(params.precision, nbar)
+        achieved = n * B / (kt["ms_lookup"] * 1e-3) / 1e9
+        traffic = measured_traffic(kind, n)
+        return {
+            "value": n / sec, "ms_per_step": sec * 1e3,
+            "params": params.as_dict(), "kernel_ms": kt,
+            "roofline": {"bound": "hbm", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic,
+                         "bytes_per_lookup": B},
+        }
+
+    plain = tuned = None
+    if args.only in (None, "plain"):
+        p_plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
+                                 block_size=256, lookups_per_thread=1,
+                                 lds_stage=0, sort_threshold=xs.INT64_MAX,
+                                 queue=xs.XS_QUEUE_COMPACT)
+        log("timing plain FP64")
+        plain = measure(p_plain, "plain_fp64")
+        log(f"plain FP64: {plain['value']:.4g} lookups/s, "
+            f"{plain['ms_per_step']:.3f} ms/step")
+    if args.only in (None, "tuned"):
+        if args.params:
+            p32 = xs.make_params(xs.XS_FP32, **json.loads(args.params))
+        else:
+            p32 = xs.make_params(xs.XS_FP32, grid="hash",
+                                 sort="material_energy", block_size=256,
+                                 lookups_per_thread=2, lds_stage=0,
+                                 sort_threshold=20000,
+                                 queue=xs.XS_QUEUE_COMPACT)
+        log("timing FP32 form with", p32.as_dict())
+        tuned = measure(p32, "tuned_fp32")
+        log(f"FP32 tuned: {tuned['value']:.4g} lookups/s, "
+            f"{tuned['ms_per_step']:.3f} ms/step")
+
+    head = tuned or plain
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(t, q, args.cpu_seconds)
+        log(f"CPU oracle: {cpu['value']:.4g} lookups/s on {cpu['cores']} cores")
+
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "lookups/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if tuned else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("synthetic full-size tables: 355 nuclides x 11,303 "
+                         "points, 12 materials (4-321 nuclides), "
+                         f"{n} lookups, E log-uniform, m uniform"),
+            "n_lookups": n, "mean_nuclides": nbar,
+            "hash_bins": args.bins, "union_size": info["union_size"],
+            "table_build_s": build_s,
+        },
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "plain_fp64": plain,
+        "tuned_fp32": tuned,
+    }
+    if plain and tuned:
+        line["fp32_tuned_over_fp64_plain"] = tuned["value"] / plain["value"]
+    print(json.dumps(line), flush=True)
+    h.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

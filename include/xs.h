@@ -1,0 +1,251 @@
+/*
+ * xs.h: C interface of the MI355X (gfx950) batched macroscopic
+ * cross-section lookup library, libxs.so.
+ *
+ * The operation (paper section 5.1, the paragraph on logarithmic hash-grid
+ * bins that follows Table 1): a particle at energy E inside material m needs
+ * the macroscopic cross sections of m at E.  Every nuclide k of m is searched
+ * for the interval of its energy grid that holds E, its tabulated channels
+ * are interpolated linearly in E, and the nuclides' values are summed
+ * weighted by their densities in m:
+ *
+ *   i_k   = clamp(#{p : E_k[p] <= E} - 1, 0, n_k - 2)
+ *   Eh    = min(max(E, E_k[0]), E_k[n_k - 1])
+ *   f     = (Eh - E_k[i]) / (E_k[i+1] - E_k[i]),   g = 1 - f
+ *   s_k,c = g * X_k[i][c] + f * X_k[i+1][c]
+ *   S_c   = sum over the material list, in list order, of rho_j * s_kj,c
+ *
+ * The paper gives the particle count in flight (1e5 to ~8e6, Table 1), the
+ * number of logarithmic hash bins (100 to 100k, default 4,000), queued versus
+ * queueless control flow and a minimum sorting threshold (default 20,000) as
+ * the tunables of this kernel; they appear here as the batch size n, the
+ * hash-grid bin count, xs_lookup_active's queue mode and sort_threshold.
+ *
+ * Conventions for every entry point:
+ *  - Return value: XS_OK (0) or a negative xs_status.  No C++ exception and
+ *    no abort crosses this interface.  On error, out-parameters are left
+ *    untouched and xs_last_error() describes the failure (per thread).
+ *  - "DEVICE" pointers are HIP device memory on the current device, owned by
+ *    the caller, and must stay valid until the stream has completed the
+ *    call.  "HOST" pointers are read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Lookups are asynchronous: a fault inside a kernel surfaces at the next
+ *    synchronisation of that stream, not as a return value here.
+ *  - A table handle is immutable after creation (xs_tune only records tuned
+ *    parameters in it) and may be used from several streams at once, each
+ *    call with its own workspace.
+ */
+#ifndef XS_H
+#define XS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xs_status;
+#define XS_OK 0
+#define XS_EINVAL (-1)     /* an argument is NULL, out of range or unsupported */
+#define XS_ETABLE (-2)     /* table data rejected by xs_create_tables */
+#define XS_ENOTBUILT (-3)  /* grid type or precision not built into the handle */
+#define XS_EWORKSPACE (-4) /* workspace missing, too small or misaligned */
+#define XS_ENOMEM (-5)     /* a device or host allocation failed */
+#define XS_EHIP (-6)       /* a HIP runtime call failed */
+#define XS_ETIMEOUT (-7)   /* a bounded wait ran out (tuner cut-off, stream) */
+
+#define XS_AUTO (-1)       /* "choose for me" in xs_params fields */
+#define XS_CHANNELS 5      /* reaction channels per grid point */
+
+/* Grid search methods.  All three return the same brackets i_k. */
+#define XS_GRID_NUCLIDE 0    /* bisection of each nuclide's grid */
+#define XS_GRID_HASH 1       /* logarithmic hash bins narrow each search */
+#define XS_GRID_UNIONIZED 2  /* one search of the union grid + index table */
+
+#define XS_FP64 0  /* FP64 tables, arithmetic and output */
+#define XS_FP32 1  /* FP32 channels and densities, FP64 search and fraction,
+                      FP32 interpolation, Kahan-compensated FP32 sum, FP32
+                      output */
+
+/* Reordering of lookups before the lookup kernel (never changes values). */
+#define XS_SORT_NONE 0
+#define XS_SORT_MATERIAL 1
+#define XS_SORT_ENERGY 2
+#define XS_SORT_MATERIAL_ENERGY 3
+
+/* xs_lookup_active: how inactive slots are skipped. */
+#define XS_QUEUE_COMPACT 0     /* queued: compact active lookups, then look up */
+#define XS_QUEUE_PREDICATED 1  /* queueless: every slot's lane checks its flag */
+
+/* Optional structures built by xs_create_tables. */
+#define XS_BUILD_FP32 1u
+#define XS_BUILD_HASH 2u
+#define XS_BUILD_UNIONIZED 4u
+
+typedef struct xs_tables_s* xs_tables_t;
+
+/* Table description: all pointers HOST, read during xs_create_tables only.
+ * Requirements (else XS_ETABLE):
+ *  - 1 <= n_nuclides; n_channels == 5;
+ *  - grid_offsets[0] == 0, n_k = grid_offsets[k+1] - grid_offsets[k] >= 2,
+ *    total points < 2^31;
+ *  - energy: finite, > 0 and strictly increasing within each nuclide;
+ *  - xs: [total points][5] point-major, finite and >= 0;
+ *  - 1 <= n_materials <= 65536; mat_offsets[0] == 0, sizes L_m >= 1;
+ *  - mat_nuclides: ids in [0, n_nuclides), no id twice within a material,
+ *    any order (the sum follows this list order);
+ *  - mat_density: finite and > 0;
+ *  - n_hash_bins in [1, 100000] when XS_BUILD_HASH is set (the paper's range
+ *    is 100 to 100k; 1 bin makes every search a full bisection). */
+typedef struct {
+  int32_t n_nuclides;
+  int32_t n_channels;
+  const int64_t* grid_offsets; /* [n_nuclides + 1] */
+  const double* energy;        /* [grid_offsets[n_nuclides]] */
+  const double* xs;            /* [grid_offsets[n_nuclides] * 5] */
+  int32_t n_materials;
+  const int32_t* mat_offsets;  /* [n_materials + 1] */
+  const int32_t* mat_nuclides; /* [mat_offsets[n_materials]] */
+  const double* mat_density;   /* [mat_offsets[n_materials]] */
+  uint32_t build_flags;        /* XS_BUILD_* bits */
+  int32_t n_hash_bins;
+} xs_table_desc;
+
+/* Launch and method parameters of one lookup call.  Every field except
+ * `precision` may be XS_AUTO (or 0 for block_size / lookups_per_thread), in
+ * which case the value recorded by xs_tune for this precision and batch size
+ * is used, else the library default (grid HASH if built else NUCLIDE, sort
+ * MATERIAL_ENERGY at n >= 20,000, block 256, 1 lookup per thread).  The
+ * choice never changes the results: every combination returns the same
+ * indices and, within one precision, bit-identical sums. */
+typedef struct {
+  int32_t precision;          /* XS_FP64 or XS_FP32 (output element type) */
+  int32_t grid;               /* XS_GRID_* */
+  int32_t sort;               /* XS_SORT_* */
+  int32_t block_size;         /* 64..1024, multiple of 64; at most 512 when
+                                 lookups_per_thread > 2 and 256 when > 4 */
+  int32_t lookups_per_thread; /* 1..8 */
+  int32_t lds_stage;          /* 0 or 1: stage grid segments in LDS */
+  int64_t sort_threshold;     /* sort only when n >= sort_threshold
+                                 (0 = always, INT64_MAX = never) */
+  int32_t queue;              /* xs_lookup_active only: XS_QUEUE_* */
+  int32_t reserved;           /* must be 0 */
+} xs_params;
+
+/* Sizes of a built handle. */
+typedef struct {
+  int32_t n_nuclides, n_materials, max_material_size, n_hash_bins;
+  int64_t n_points;          /* total grid points over all nuclides */
+  int64_t union_size;        /* points of the union grid (0 if not built) */
+  uint32_t build_flags;
+  uint32_t reserved;
+  double e_min, e_max;       /* smallest first and largest last grid energy */
+  size_t bytes_grid;         /* search grid (FP64 energies) */
+  size_t bytes_fp64;         /* FP64 interpolation records */
+  size_t bytes_fp32;         /* FP32 interpolation records */
+  size_t bytes_materials;    /* material lists */
+  size_t bytes_hash;         /* hash-bin index table */
+  size_t bytes_union;        /* union grid + its index table */
+} xs_table_info_t;
+
+/* Per-stage device time of lookup calls made between xs_profile_begin and
+ * xs_profile_end on the handle (HIP events on each call's stream). */
+typedef struct {
+  double ms_sort;      /* key build + radix passes (+ compaction) */
+  double ms_lookup;    /* the lookup kernel itself */
+  double ms_total;     /* first to last event of each call, summed */
+  int64_t calls;       /* lookup calls recorded */
+  int64_t sorted_calls;/* calls that sorted */
+  int64_t lookups;     /* lookups processed by the recorded calls */
+} xs_profile_t;
+
+/* ---- tables ------------------------------------------------------------ */
+
+/* Validates `desc`, copies every array to device memory, builds the optional
+ * FP32 records, hash-bin table (paper section 5.1: "logarithmic hash grid
+ * bins") and unionized grid, and returns a handle.  Synchronises `stream`
+ * before returning; the host arrays may be freed afterwards.
+ * Errors: XS_EINVAL (NULL), XS_ETABLE (data), XS_ENOMEM, XS_EHIP. */
+xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
+                           xs_tables_t* out);
+
+/* Frees every device allocation of the handle.  The caller must have
+ * completed all work that uses it.  NULL is accepted (no-op). */
+xs_status xs_destroy_tables(xs_tables_t tables);
+
+/* Sizes and byte counts of the handle. */
+xs_status xs_table_info(xs_tables_t tables, xs_table_info_t* info);
+
+/* ---- parameters ---------------------------------------------------------- */
+
+/* Fills *p with XS_AUTO everywhere and the given precision. */
+xs_status xs_params_default(xs_params* p, int32_t precision);
+
+/* Resolves XS_AUTO fields for a batch of n lookups exactly as
+ * xs_lookup_batch would, and checks the result (XS_EINVAL for out-of-range
+ * values, XS_ENOTBUILT for a grid or precision the handle lacks).  `in` may
+ * be NULL (all automatic, FP64). */
+xs_status xs_resolve_params(xs_tables_t tables, int64_t n,
+                            const xs_params* in, xs_params* out);
+
+/* Bytes of device workspace xs_lookup_batch / xs_lookup_active need for n
+ * lookups with these parameters (0 when no sort or compaction runs). */
+xs_status xs_workspace_size(xs_tables_t tables, int64_t n,
+                            const xs_params* params, size_t* bytes);
+
+/* ---- lookups ------------------------------------------------------------- */
+
+/* n lookups: out[q][c] = S_c(d_E[q], d_mat[q]) for q < n, c < 5.
+ *  d_E   DEVICE double [n];  d_mat DEVICE int32 [n];
+ *  d_out DEVICE [n][5] double (XS_FP64) or float (XS_FP32);
+ *  params may be NULL (all automatic, FP64);
+ *  d_ws  DEVICE, 256-byte aligned, ws_bytes >= xs_workspace_size(...).
+ * A lookup with E not finite and > 0, or m outside [0, n_materials), gets
+ * NaN in all five channels.  n == 0 is a no-op.  Output order is input order
+ * whatever the sort policy. */
+xs_status xs_lookup_batch(xs_tables_t tables, int64_t n, const double* d_E,
+                          const int32_t* d_mat, void* d_out,
+                          const xs_params* params, void* d_ws, size_t ws_bytes,
+                          void* stream);
+
+/* As xs_lookup_batch for the slots whose d_active[q] != 0 (DEVICE uint8
+ * [n]); the outputs of other slots are not written.  params->queue picks
+ * compaction of the active slots (queued) or a predicated pass over all
+ * slots (queueless), paper section 5.1 "queuing logic". */
+xs_status xs_lookup_active(xs_tables_t tables, int64_t n, const double* d_E,
+                           const int32_t* d_mat, const uint8_t* d_active,
+                           void* d_out, const xs_params* params, void* d_ws,
+                           size_t ws_bytes, void* stream);
+
+/* Validation path: writes the bracket i_k of every (lookup, nuclide) pair
+ * found with the given grid method.  d_idx_offsets DEVICE int64 [n+1] is the
+ * prefix sum of the material sizes of the lookups; lookup q writes
+ * d_idx[d_idx_offsets[q] + j] for its j-th nuclide (list order).  A lookup
+ * with invalid E writes -1; one with an invalid material writes nothing. */
+xs_status xs_lookup_indices(xs_tables_t tables, int64_t n, const double* d_E,
+                            const int32_t* d_mat, const int64_t* d_idx_offsets,
+                            int32_t* d_idx, int32_t grid, void* stream);
+
+/* ---- measurement --------------------------------------------------------- */
+
+/* Starts recording per-stage HIP events for subsequent lookup calls on this
+ * handle (adds two events per stage per call). */
+xs_status xs_profile_begin(xs_tables_t tables);
+
+/* Synchronises the recorded events, sums them into *out and stops
+ * recording. */
+xs_status xs_profile_end(xs_tables_t tables, xs_profile_t* out);
+
+/* ---- errors ------------------------------------------------------------ */
+
+const char* xs_status_string(xs_status status);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* xs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XS_H */

@@ -1,0 +1,660 @@
+// C entry points of libxs: argument and table validation, table packing and
+// upload, parameter resolution, the lookup pipeline (optional sort or
+// compaction, then the lookup kernel) and per-stage event timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+
+#include "xs_internal.h"
+
+namespace xs {
+
+namespace {
+thread_local char g_error[512] = "";
+}
+
+xs_status fail(xs_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_error, sizeof(g_error), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+void clear_error() { g_error[0] = '\0'; }
+
+namespace {
+
+int ceil_log2(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+int64_t double_bits(double x) {
+  int64_t b;
+  std::memcpy(&b, &x, sizeof(b));
+  return b;
+}
+
+// Frees what a partially built handle holds.
+void release(xs_tables_s* h) {
+  for (void* p : h->allocations) (void)hipFree(p);
+  h->allocations.clear();
+  for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+  h->event_pool.clear();
+  for (auto& c : h->prof)
+    for (hipEvent_t e : c.ev) (void)hipEventDestroy(e);
+  h->prof.clear();
+}
+
+template <class T>
+xs_status upload(xs_tables_s* h, const T* src, size_t count, T** dst,
+                 hipStream_t s) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 1);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess)
+    return fail(XS_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes,
+                hipGetErrorString(e));
+  h->allocations.push_back(p);
+  if (count) XS_HIP(hipMemcpyAsync(p, src, count * sizeof(T),
+                                   hipMemcpyHostToDevice, s));
+  *dst = (T*)p;
+  return XS_OK;
+}
+
+xs_status alloc_dev(xs_tables_s* h, size_t bytes, void** dst) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 1));
+  if (e != hipSuccess)
+    return fail(XS_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes,
+                hipGetErrorString(e));
+  h->allocations.push_back(p);
+  *dst = p;
+  return XS_OK;
+}
+
+// Host-only checks of a table description (no HIP call).
+xs_status validate_desc(const xs_table_desc* d) {
+  if (!d) return fail(XS_EINVAL, "desc is NULL");
+  if (d->n_nuclides < 1) return fail(XS_ETABLE, "n_nuclides must be >= 1");
+  if (d->n_channels != XS_CHANNELS)
+    return fail(XS_ETABLE, "n_channels must be %d", XS_CHANNELS);
+  if (!d->grid_offsets || !d->energy || !d->xs)
+    return fail(XS_EINVAL, "grid arrays must not be NULL");
+  if (d->n_materials < 1 || d->n_materials > 65536)
+    return fail(XS_ETABLE, "n_materials must be in [1, 65536]");
+  if (!d->mat_offsets || !d->mat_nuclides || !d->mat_density)
+    return fail(XS_EINVAL, "material arrays must not be NULL");
+  if (d->build_flags & ~(XS_BUILD_FP32 | XS_BUILD_HASH | XS_BUILD_UNIONIZED))
+    return fail(XS_EINVAL, "unknown build flag bits 0x%x", d->build_flags);
+  if ((d->build_flags & XS_BUILD_HASH) &&
+      (d->n_hash_bins < 1 || d->n_hash_bins > 100000))
+    return fail(XS_EINVAL, "n_hash_bins must be in [1, 100000]");
+
+  const int K = d->n_nuclides;
+  if (d->grid_offsets[0] != 0) return fail(XS_ETABLE, "grid_offsets[0] != 0");
+  for (int k = 0; k < K; ++k) {
+    const int64_t a = d->grid_offsets[k], b = d->grid_offsets[k + 1];
+    if (b - a < 2)
+      return fail(XS_ETABLE, "nuclide %d has %lld grid points (needs >= 2)", k,
+                  (long long)(b - a));
+    if (b >= (int64_t)0x7fffffff)
+      return fail(XS_ETABLE, "more than 2^31-2 grid points in total");
+    for (int64_t p = a; p < b; ++p) {
+      const double e = d->energy[p];
+      if (!std::isfinite(e) || !(e > 0.0))
+        return fail(XS_ETABLE, "nuclide %d point %lld: energy %g not finite "
+                    "and > 0", k, (long long)(p - a), e);
+      if (p > a && !(d->energy[p - 1] < e))
+        return fail(XS_ETABLE, "nuclide %d: energies not strictly increasing "
+                    "at point %lld", k, (long long)(p - a));
+      for (int c = 0; c < XS_CHANNELS; ++c) {
+        const double x = d->xs[p * XS_CHANNELS + c];
+        if (!std::isfinite(x) || x < 0.0)
+          return fail(XS_ETABLE, "nuclide %d point %lld channel %d: value %g "
+                      "not finite and >= 0", k, (long long)(p - a), c, x);
+      }
+    }
+  }
+  const int M = d->n_materials;
+  if (d->mat_offsets[0] != 0) return fail(XS_ETABLE, "mat_offsets[0] != 0");
+  std::vector<int32_t> seen(K, -1);
+  for (int m = 0; m < M; ++m) {
+    const int32_t a = d->mat_offsets[m], b = d->mat_offsets[m + 1];
+    if (b - a < 1) return fail(XS_ETABLE, "material %d is empty", m);
+    for (int32_t j = a; j < b; ++j) {
+      const int32_t k = d->mat_nuclides[j];
+      if (k < 0 || k >= K)
+        return fail(XS_ETABLE, "material %d: nuclide id %d out of range", m, k);
+      if (seen[k] == m)
+        return fail(XS_ETABLE, "material %d lists nuclide %d twice", m, k);
+      seen[k] = m;
+      const double r = d->mat_density[j];
+      if (!std::isfinite(r) || !(r > 0.0))
+        return fail(XS_ETABLE, "material %d: density %g not finite and > 0", m,
+                    r);
+    }
+  }
+  return XS_OK;
+}
+
+xs_status check_handle(xs_tables_t h) {
+  if (!h) return fail(XS_EINVAL, "table handle is NULL");
+  return XS_OK;
+}
+
+const xs_params* nearest_tuned(const xs_tables_s* h, int prec, int64_t n) {
+  const int want = n > 0 ? 63 - __builtin_clzll((unsigned long long)n) : 0;
+  int best = -1, dist = 1 << 30;
+  for (int b = 0; b < kBuckets; ++b) {
+    if (!h->tuned_valid[prec][b]) continue;
+    const int dd = std::abs(b - want);
+    if (dd < dist) {
+      dist = dd;
+      best = b;
+    }
+  }
+  return best < 0 ? nullptr : &h->tuned[prec][best];
+}
+
+xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
+                  xs_params* out) {
+  xs_params p;
+  if (in) {
+    p = *in;
+  } else {
+    xs_params_default(&p, XS_FP64);
+  }
+  if (p.precision != XS_FP64 && p.precision != XS_FP32)
+    return fail(XS_EINVAL, "precision must be XS_FP64 or XS_FP32");
+  if (p.precision == XS_FP32 && !h->d.rec32)
+    return fail(XS_ENOTBUILT, "FP32 tables were not built (XS_BUILD_FP32)");
+  if (p.reserved != 0) return fail(XS_EINVAL, "reserved field must be 0");
+
+  xs_params t;
+  bool have_tuned = false;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    const xs_params* tp = nearest_tuned(h, p.precision, n);
+    if (tp) {
+      t = *tp;
+      have_tuned = true;
+    }
+  }
+  if (!have_tuned) {
+    t.precision = p.precision;
+    t.grid = h->d.B > 0 ? XS_GRID_HASH : XS_GRID_NUCLIDE;
+    t.sort = XS_SORT_MATERIAL_ENERGY;
+    t.block_size = 256;
+    t.lookups_per_thread = 1;
+    t.lds_stage = 0;
+    t.sort_threshold = 20000;
+    t.queue = XS_QUEUE_COMPACT;
+    t.reserved = 0;
+  }
+  if (p.grid == XS_AUTO) p.grid = t.grid;
+  if (p.sort == XS_AUTO) p.sort = t.sort;
+  if (p.block_size == 0 || p.block_size == XS_AUTO) p.block_size = t.block_size;
+  if (p.lookups_per_thread == 0 || p.lookups_per_thread == XS_AUTO)
+    p.lookups_per_thread = t.lookups_per_thread;
+  if (p.lds_stage == XS_AUTO) p.lds_stage = t.lds_stage;
+  if (p.sort_threshold < 0) p.sort_threshold = t.sort_threshold;
+  if (p.queue == XS_AUTO) p.queue = t.queue;
+
+  if (p.grid < 0 || p.grid > 2) return fail(XS_EINVAL, "unknown grid %d", p.grid);
+  if (p.grid == XS_GRID_HASH && h->d.B == 0)
+    return fail(XS_ENOTBUILT, "hash grid was not built (XS_BUILD_HASH)");
+  if (p.grid == XS_GRID_UNIONIZED && h->d.U == 0)
+    return fail(XS_ENOTBUILT, "unionized grid was not built (XS_BUILD_UNIONIZED)");
+  if (p.sort < 0 || p.sort > 3) return fail(XS_EINVAL, "unknown sort %d", p.sort);
+  if (p.block_size < 64 || p.block_size > 1024 || p.block_size % 64)
+    return fail(XS_EINVAL, "block_size %d not in 64..1024 step 64", p.block_size);
+  if (p.lookups_per_thread < 1 || p.lookups_per_thread > 8)
+    return fail(XS_EINVAL, "lookups_per_thread %d not in 1..8",
+                p.lookups_per_thread);
+  {
+    const int lpt = p.lookups_per_thread;
+    const int max_block = lpt <= 2 ? 1024 : (lpt <= 4 ? 512 : 256);
+    if (p.block_size > max_block)
+      return fail(XS_EINVAL, "block_size %d too large for %d lookups per thread "
+                  "(max %d)", p.block_size, lpt, max_block);
+  }
+  if (p.lds_stage != 0 && p.lds_stage != 1)
+    return fail(XS_EINVAL, "lds_stage must be 0 or 1");
+  if (p.lds_stage == 1)
+    return fail(XS_EINVAL, "lds_stage = 1 is not available in this build");
+  if (p.queue != XS_QUEUE_COMPACT && p.queue != XS_QUEUE_PREDICATED)
+    return fail(XS_EINVAL, "unknown queue mode %d", p.queue);
+  *out = p;
+  return XS_OK;
+}
+
+SortKey make_sort_key(const xs_tables_s* h, int sort, bool flag) {
+  SortKey k{};
+  k.M = h->d.M;
+  k.flag_bit = flag ? 1 : 0;
+  const int mb = ceil_log2(h->d.M);
+  switch (sort) {
+    case XS_SORT_MATERIAL:
+      k.mat_bits = std::max(mb, 1);
+      k.e_bits = 0;
+      break;
+    case XS_SORT_ENERGY:
+      k.mat_bits = 0;
+      k.e_bits = 16 - k.flag_bit;
+      break;
+    default: {
+      k.mat_bits = mb;
+      const int target = mb + k.flag_bit + 8 <= 16 ? 16 : 32;
+      k.e_bits = target - mb - k.flag_bit;
+      break;
+    }
+  }
+  k.e_bits_min = double_bits(h->info.e_min);
+  if (k.e_bits > 0) {
+    const int64_t span = double_bits(h->info.e_max) - k.e_bits_min;
+    int s = 0;
+    while ((span >> s) >= (int64_t(1) << k.e_bits)) ++s;
+    k.e_shift = s;
+  }
+  k.total_bits = k.mat_bits + k.e_bits + k.flag_bit;
+  return k;
+}
+
+hipEvent_t take_event(xs_tables_s* h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
+                        const int32_t* mat, const uint8_t* active, bool masked,
+                        void* out, const xs_params* params, void* ws,
+                        size_t ws_bytes, void* stream) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (n < 0) return fail(XS_EINVAL, "n must be >= 0");
+  if (n > 0x7fffffffLL) return fail(XS_EINVAL, "n must be < 2^31");
+  xs_params p;
+  if (xs_status st = resolve(h, n, params, &p)) return st;
+  if (n == 0) return XS_OK;
+  if (!E || !mat || !out) return fail(XS_EINVAL, "query or output pointer is NULL");
+  if (masked && !active) return fail(XS_EINVAL, "active mask is NULL");
+  int dev = -1;
+  XS_HIP(hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(XS_EINVAL, "current device %d is not the tables' device %d",
+                dev, h->device);
+
+  const bool do_sort = p.sort != XS_SORT_NONE && n >= p.sort_threshold;
+  const bool compact = masked && !do_sort && p.queue == XS_QUEUE_COMPACT;
+  const SortKey key = do_sort ? make_sort_key(h, p.sort, masked) : SortKey{};
+  const size_t need = do_sort   ? sort_workspace_bytes(n, key.total_bits)
+                      : compact ? compact_workspace_bytes(n)
+                                : 0;
+  if (need > 0) {
+    if (!ws || ws_bytes < need)
+      return fail(XS_EWORKSPACE, "workspace of %zu bytes needed, %zu given",
+                  need, ws ? ws_bytes : (size_t)0);
+    if ((uintptr_t)ws % 256)
+      return fail(XS_EWORKSPACE, "workspace must be 256-byte aligned");
+  }
+  hipStream_t s = (hipStream_t)stream;
+
+  ProfCall pc{};
+  const bool prof = h->profiling;
+  if (prof) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    for (auto& e : pc.ev) {
+      e = take_event(h);
+      if (!e) return fail(XS_EHIP, "hipEventCreate failed");
+    }
+    pc.sorted = do_sort || compact;
+    pc.n = n;
+  }
+  if (prof) XS_HIP(hipEventRecord(pc.ev[0], s));
+
+  LookupArgs a{n, E, mat, nullptr, nullptr, masked ? active : nullptr, out};
+  if (do_sort) {
+    XS_HIP(launch_sort(key, n, E, mat, masked ? active : nullptr, ws, &a.perm, s));
+  } else if (compact) {
+    XS_HIP(launch_compact(n, active, ws, &a.perm, &a.count_dev, s));
+    a.active = nullptr;
+  }
+  if (prof) XS_HIP(hipEventRecord(pc.ev[1], s));
+  hipError_t e;
+  switch (p.grid) {
+    case XS_GRID_NUCLIDE: e = launch_lookup_nuclide(h->d, p, a, s); break;
+    case XS_GRID_HASH: e = launch_lookup_hash(h->d, p, a, s); break;
+    default: e = launch_lookup_union(h->d, p, a, s); break;
+  }
+  if (e != hipSuccess)
+    return fail(XS_EHIP, "lookup kernel launch failed: %s", hipGetErrorString(e));
+  if (prof) {
+    XS_HIP(hipEventRecord(pc.ev[2], s));
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->prof.push_back(pc);
+  }
+  return XS_OK;
+}
+
+}  // namespace
+}  // namespace xs
+
+using namespace xs;
+
+extern "C" {
+
+xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
+                           xs_tables_t* out) {
+  clear_error();
+  if (!out) return fail(XS_EINVAL, "out is NULL");
+  if (xs_status st = validate_desc(desc)) return st;
+  const int K = desc->n_nuclides, M = desc->n_materials;
+  const int64_t P = desc->grid_offsets[K];
+  const int32_t L = desc->mat_offsets[M];
+  hipStream_t s = (hipStream_t)stream;
+
+  auto* h = new (std::nothrow) xs_tables_s();
+  if (!h) return fail(XS_ENOMEM, "host allocation failed");
+  auto cleanup = [&](xs_status st) {
+    if (s) (void)hipStreamSynchronize(s); else (void)hipDeviceSynchronize();
+    release(h);
+    delete h;
+    return st;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess)
+    return cleanup(fail(XS_EHIP, "no HIP device available"));
+
+  // Host packing.
+  std::vector<Rec64> rec64(P);
+  std::vector<Rec32> rec32((desc->build_flags & XS_BUILD_FP32) ? P : 0);
+  double e_min = std::numeric_limits<double>::infinity(), e_max = 0.0;
+  std::vector<int32_t> goff(K + 1);
+  for (int k = 0; k <= K; ++k) goff[k] = (int32_t)desc->grid_offsets[k];
+  for (int k = 0; k < K; ++k) {
+    e_min = std::min(e_min, desc->energy[goff[k]]);
+    e_max = std::max(e_max, desc->energy[goff[k + 1] - 1]);
+  }
+  for (int64_t p = 0; p < P; ++p) {
+    for (int c = 0; c < XS_CHANNELS; ++c) rec64[p].x[c] = desc->xs[p * 5 + c];
+    rec64[p].e = desc->energy[p];
+    if (!rec32.empty()) {
+      for (int c = 0; c < XS_CHANNELS; ++c)
+        rec32[p].x[c] = (float)desc->xs[p * 5 + c];
+      rec32[p].pad = 0.0f;
+      rec32[p].e = desc->energy[p];
+    }
+  }
+  std::vector<MatRec> mrec(L);
+  int max_L = 0;
+  for (int m = 0; m < M; ++m) {
+    max_L = std::max(max_L, desc->mat_offsets[m + 1] - desc->mat_offsets[m]);
+    for (int32_t j = desc->mat_offsets[m]; j < desc->mat_offsets[m + 1]; ++j) {
+      const int k = desc->mat_nuclides[j];
+      mrec[j].base = goff[k];
+      mrec[j].n = goff[k + 1] - goff[k];
+      mrec[j].k = k;
+      mrec[j].rho32 = (float)desc->mat_density[j];
+    }
+  }
+
+  DevTables& d = h->d;
+  d.K = K;
+  d.M = M;
+  double* E_dev;
+  Rec64* r64;
+  int32_t *moff, *goff_dev;
+  MatRec* mr;
+  double* rho;
+  xs_status st;
+  if ((st = upload(h, desc->energy, (size_t)P, &E_dev, s))) return cleanup(st);
+  if ((st = upload(h, rec64.data(), rec64.size(), &r64, s))) return cleanup(st);
+  if ((st = upload(h, desc->mat_offsets, (size_t)M + 1, &moff, s))) return cleanup(st);
+  if ((st = upload(h, mrec.data(), mrec.size(), &mr, s))) return cleanup(st);
+  if ((st = upload(h, desc->mat_density, (size_t)L, &rho, s))) return cleanup(st);
+  if ((st = upload(h, goff.data(), goff.size(), &goff_dev, s))) return cleanup(st);
+  d.E = E_dev;
+  d.rec64 = r64;
+  d.moff = moff;
+  d.mrec = mr;
+  d.rho64 = rho;
+  if (!rec32.empty()) {
+    Rec32* r32;
+    if ((st = upload(h, rec32.data(), rec32.size(), &r32, s))) return cleanup(st);
+    d.rec32 = r32;
+  }
+
+  xs_table_info_t& info = h->info;
+  info.n_nuclides = K;
+  info.n_materials = M;
+  info.max_material_size = max_L;
+  info.n_points = P;
+  info.build_flags = desc->build_flags;
+  info.e_min = e_min;
+  info.e_max = e_max;
+  info.bytes_grid = (size_t)P * 8;
+  info.bytes_fp64 = (size_t)P * sizeof(Rec64);
+  info.bytes_fp32 = rec32.size() * sizeof(Rec32);
+  info.bytes_materials = (size_t)(M + 1) * 4 + (size_t)L * (sizeof(MatRec) + 8);
+
+  if (desc->build_flags & XS_BUILD_HASH) {
+    const int B = desc->n_hash_bins;
+    d.B = B;
+    d.ln_emin = std::log(e_min);
+    const double span = std::log(e_max) - d.ln_emin;
+    d.inv_dln = (double)B / span;
+    void* H;
+    const size_t bytes = (size_t)(B + 1) * K * 4;
+    if ((st = alloc_dev(h, bytes, &H))) return cleanup(st);
+    d.H = (const int32_t*)H;
+    hipError_t e = launch_hash_build(d, goff_dev, span / B, (int32_t*)H, s);
+    if (e != hipSuccess)
+      return cleanup(fail(XS_EHIP, "hash build launch failed: %s",
+                          hipGetErrorString(e)));
+    info.n_hash_bins = B;
+    info.bytes_hash = bytes;
+  }
+  if (desc->build_flags & XS_BUILD_UNIONIZED) {
+    std::vector<double> u(desc->energy, desc->energy + P);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    const int64_t U = (int64_t)u.size();
+    double* u_dev;
+    if ((st = upload(h, u.data(), u.size(), &u_dev, s))) return cleanup(st);
+    void* uidx;
+    const size_t bytes = (size_t)U * K * 4;
+    if ((st = alloc_dev(h, bytes, &uidx))) return cleanup(st);
+    d.U = U;
+    d.u = u_dev;
+    d.uidx = (const int32_t*)uidx;
+    hipError_t e = launch_union_index(d, goff_dev, (int32_t*)uidx, s);
+    if (e != hipSuccess)
+      return cleanup(fail(XS_EHIP, "union index launch failed: %s",
+                          hipGetErrorString(e)));
+    info.union_size = U;
+    info.bytes_union = (size_t)U * 8 + bytes;
+  }
+  hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
+  if (e != hipSuccess)
+    return cleanup(fail(XS_EHIP, "table build failed: %s", hipGetErrorString(e)));
+  *out = h;
+  return XS_OK;
+}
+
+xs_status xs_destroy_tables(xs_tables_t h) {
+  clear_error();
+  if (!h) return XS_OK;
+  release(h);
+  delete h;
+  return XS_OK;
+}
+
+xs_status xs_table_info(xs_tables_t h, xs_table_info_t* info) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (!info) return fail(XS_EINVAL, "info is NULL");
+  *info = h->info;
+  return XS_OK;
+}
+
+xs_status xs_params_default(xs_params* p, int32_t precision) {
+  clear_error();
+  if (!p) return fail(XS_EINVAL, "params is NULL");
+  if (precision != XS_FP64 && precision != XS_FP32)
+    return fail(XS_EINVAL, "precision must be XS_FP64 or XS_FP32");
+  p->precision = precision;
+  p->grid = XS_AUTO;
+  p->sort = XS_AUTO;
+  p->block_size = 0;
+  p->lookups_per_thread = 0;
+  p->lds_stage = XS_AUTO;
+  p->sort_threshold = -1;
+  p->queue = XS_AUTO;
+  p->reserved = 0;
+  return XS_OK;
+}
+
+xs_status xs_resolve_params(xs_tables_t h, int64_t n, const xs_params* in,
+                            xs_params* out) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (!out) return fail(XS_EINVAL, "out is NULL");
+  if (n < 0) return fail(XS_EINVAL, "n must be >= 0");
+  return resolve(h, n, in, out);
+}
+
+xs_status xs_workspace_size(xs_tables_t h, int64_t n, const xs_params* params,
+                            size_t* bytes) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (!bytes) return fail(XS_EINVAL, "bytes is NULL");
+  if (n < 0 || n > 0x7fffffffLL) return fail(XS_EINVAL, "n out of range");
+  xs_params p;
+  if (xs_status st = resolve(h, n, params, &p)) return st;
+  size_t b = 0;
+  if (n > 0) {
+    // Enough for either entry point: a sort (with or without the active
+    // flag) or a compaction.
+    if (p.sort != XS_SORT_NONE && n >= p.sort_threshold)
+      b = sort_workspace_bytes(n, 32);
+    else
+      b = compact_workspace_bytes(n);
+  }
+  *bytes = b;
+  return XS_OK;
+}
+
+xs_status xs_lookup_batch(xs_tables_t h, int64_t n, const double* d_E,
+                          const int32_t* d_mat, void* d_out,
+                          const xs_params* params, void* d_ws, size_t ws_bytes,
+                          void* stream) {
+  return lookup_common(h, n, d_E, d_mat, nullptr, false, d_out, params, d_ws,
+                       ws_bytes, stream);
+}
+
+xs_status xs_lookup_active(xs_tables_t h, int64_t n, const double* d_E,
+                           const int32_t* d_mat, const uint8_t* d_active,
+                           void* d_out, const xs_params* params, void* d_ws,
+                           size_t ws_bytes, void* stream) {
+  return lookup_common(h, n, d_E, d_mat, d_active, true, d_out, params, d_ws,
+                       ws_bytes, stream);
+}
+
+xs_status xs_lookup_indices(xs_tables_t h, int64_t n, const double* d_E,
+                            const int32_t* d_mat, const int64_t* d_idx_offsets,
+                            int32_t* d_idx, int32_t grid, void* stream) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (n < 0 || n > 0x7fffffffLL) return fail(XS_EINVAL, "n out of range");
+  if (grid < 0 || grid > 2) return fail(XS_EINVAL, "unknown grid %d", grid);
+  if (grid == XS_GRID_HASH && h->d.B == 0)
+    return fail(XS_ENOTBUILT, "hash grid was not built");
+  if (grid == XS_GRID_UNIONIZED && h->d.U == 0)
+    return fail(XS_ENOTBUILT, "unionized grid was not built");
+  if (n == 0) return XS_OK;
+  if (!d_E || !d_mat || !d_idx_offsets || !d_idx)
+    return fail(XS_EINVAL, "a pointer is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  switch (grid) {
+    case XS_GRID_NUCLIDE:
+      e = launch_indices_nuclide(h->d, n, d_E, d_mat, d_idx_offsets, d_idx, s);
+      break;
+    case XS_GRID_HASH:
+      e = launch_indices_hash(h->d, n, d_E, d_mat, d_idx_offsets, d_idx, s);
+      break;
+    default:
+      e = launch_indices_union(h->d, n, d_E, d_mat, d_idx_offsets, d_idx, s);
+      break;
+  }
+  if (e != hipSuccess)
+    return fail(XS_EHIP, "index kernel launch failed: %s", hipGetErrorString(e));
+  return XS_OK;
+}
+
+xs_status xs_profile_begin(xs_tables_t h) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  std::lock_guard<std::mutex> lk(h->mu);
+  for (auto& c : h->prof)
+    for (hipEvent_t e : c.ev) h->event_pool.push_back(e);
+  h->prof.clear();
+  h->profiling = true;
+  return XS_OK;
+}
+
+xs_status xs_profile_end(xs_tables_t h, xs_profile_t* out) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (!out) return fail(XS_EINVAL, "out is NULL");
+  std::lock_guard<std::mutex> lk(h->mu);
+  h->profiling = false;
+  xs_profile_t r{};
+  for (auto& c : h->prof) {
+    XS_HIP(hipEventSynchronize(c.ev[2]));
+    float a = 0, b = 0, t = 0;
+    XS_HIP(hipEventElapsedTime(&a, c.ev[0], c.ev[1]));
+    XS_HIP(hipEventElapsedTime(&b, c.ev[1], c.ev[2]));
+    XS_HIP(hipEventElapsedTime(&t, c.ev[0], c.ev[2]));
+    r.ms_sort += a;
+    r.ms_lookup += b;
+    r.ms_total += t;
+    r.calls += 1;
+    r.sorted_calls += c.sorted ? 1 : 0;
+    r.lookups += c.n;
+  }
+  for (auto& c : h->prof)
+    for (hipEvent_t e : c.ev) h->event_pool.push_back(e);
+  h->prof.clear();
+  *out = r;
+  return XS_OK;
+}
+
+const char* xs_status_string(xs_status st) {
+  switch (st) {
+    case XS_OK: return "XS_OK";
+    case XS_EINVAL: return "XS_EINVAL: invalid argument";
+    case XS_ETABLE: return "XS_ETABLE: table data rejected";
+    case XS_ENOTBUILT: return "XS_ENOTBUILT: structure not built";
+    case XS_EWORKSPACE: return "XS_EWORKSPACE: workspace missing or too small";
+    case XS_ENOMEM: return "XS_ENOMEM: allocation failed";
+    case XS_EHIP: return "XS_EHIP: HIP runtime error";
+    case XS_ETIMEOUT: return "XS_ETIMEOUT: time limit reached";
+    default: return "unknown xs_status";
+  }
+}
+
+const char* xs_last_error(void) { return g_error; }
+
+}  // extern "C"

@@ -1,0 +1,168 @@
+// Internal declarations of libxs: device table layout, kernels' launch
+// helpers and the host-side handle.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "xs.h"
+
+namespace xs {
+
+// ---- device table layout -------------------------------------------------
+//
+// Search grid: every nuclide's energies back to back (FP64), dense so that
+// bisection probes share cache lines.  Interpolation reads a record pair
+// (point i and i+1) that carries both energies and the five channels, so a
+// bracket costs one contiguous 96-byte (FP64) or 64-byte (FP32) read.
+
+struct alignas(16) Rec64 {  // 48 bytes
+  double x[XS_CHANNELS];
+  double e;
+};
+struct alignas(16) Rec32 {  // 32 bytes
+  float x[XS_CHANNELS];
+  float pad;
+  double e;
+};
+static_assert(sizeof(Rec64) == 48, "Rec64 layout");
+static_assert(sizeof(Rec32) == 32, "Rec32 layout");
+
+// One entry of a material list: where the nuclide's grid starts, its length,
+// its id (row of the hash and union index tables) and its FP32 density.
+struct alignas(16) MatRec {
+  int32_t base;
+  int32_t n;
+  int32_t k;
+  float rho32;
+};
+
+struct DevTables {
+  int32_t K;                 // nuclides
+  int32_t M;                 // materials
+  const double* E;           // [P] search grid
+  const Rec64* rec64;        // [P]
+  const Rec32* rec32;        // [P] (null unless built)
+  const int32_t* moff;       // [M+1]
+  const MatRec* mrec;        // [sum L]
+  const double* rho64;       // [sum L]
+  // logarithmic hash bins
+  int32_t B;                 // bins (0 = not built)
+  double ln_emin;            // ln of the lowest grid energy
+  double inv_dln;            // B / (ln e_max - ln e_min)
+  const int32_t* H;          // [(B+1) * K]: bracket of each bin's lower edge
+  // unionized grid
+  int64_t U;                 // union points (0 = not built)
+  const double* u;           // [U]
+  const int32_t* uidx;       // [U * K]: bracket of u[j] in nuclide k
+};
+
+// ---- sort key ------------------------------------------------------------
+struct SortKey {
+  int32_t mat_bits;   // bits of the material field (0 = not in the key)
+  int32_t e_bits;     // bits of the energy field (0 = not in the key)
+  int32_t e_shift;    // right shift applied to (bits(E) - bits(e_min))
+  int32_t flag_bit;   // 1: an "inactive" flag sits above the other fields
+  int64_t e_bits_min; // IEEE bit pattern of e_min
+  int32_t M;
+  int32_t total_bits;
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per block
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+
+// ---- host handle ---------------------------------------------------------
+
+constexpr int kBuckets = 48;  // tuned parameters per floor(log2(n))
+
+struct ProfCall {
+  hipEvent_t ev[3];  // before sort, after sort, after lookup
+  bool sorted;
+  int64_t n;
+};
+
+}  // namespace xs
+
+struct xs_tables_s {
+  int device = 0;
+  xs::DevTables d{};
+  xs_table_info_t info{};
+  std::vector<void*> allocations;
+  bool tuned_valid[2][xs::kBuckets] = {};
+  xs_params tuned[2][xs::kBuckets] = {};
+  std::mutex mu;
+  bool profiling = false;
+  std::vector<xs::ProfCall> prof;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace xs {
+
+// Error reporting: records a message for xs_last_error() and returns st.
+xs_status fail(xs_status st, const char* fmt, ...);
+void clear_error();
+
+#define XS_HIP(call)                                                      \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return ::xs::fail(e_ == hipErrorOutOfMemory ? XS_ENOMEM : XS_EHIP,  \
+                        "%s failed: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+// Table builders (xs_build.hip).
+hipError_t launch_hash_build(const DevTables& t, const int32_t* goff_dev,
+                             double dln, int32_t* H, hipStream_t s);
+hipError_t launch_union_index(const DevTables& t, const int32_t* goff_dev,
+                              int32_t* uidx, hipStream_t s);
+
+// Lookup kernels (xs_lookup_*.hip).  count_dev, when not null, holds the
+// number of valid entries of perm (device-side queue length).
+struct LookupArgs {
+  int64_t n;
+  const double* E;
+  const int32_t* mat;
+  const int32_t* perm;     // null = identity
+  const int64_t* count_dev;
+  const uint8_t* active;   // null = all active
+  void* out;
+};
+hipError_t launch_lookup_nuclide(const DevTables& t, const xs_params& p,
+                                 const LookupArgs& a, hipStream_t s);
+hipError_t launch_lookup_hash(const DevTables& t, const xs_params& p,
+                              const LookupArgs& a, hipStream_t s);
+hipError_t launch_lookup_union(const DevTables& t, const xs_params& p,
+                               const LookupArgs& a, hipStream_t s);
+hipError_t launch_indices_nuclide(const DevTables& t, int64_t n,
+                                  const double* E, const int32_t* mat,
+                                  const int64_t* off, int32_t* idx,
+                                  hipStream_t s);
+hipError_t launch_indices_hash(const DevTables& t, int64_t n, const double* E,
+                               const int32_t* mat, const int64_t* off,
+                               int32_t* idx, hipStream_t s);
+hipError_t launch_indices_union(const DevTables& t, int64_t n, const double* E,
+                                const int32_t* mat, const int64_t* off,
+                                int32_t* idx, hipStream_t s);
+
+// Sort and compaction (xs_sort.hip).
+size_t sort_workspace_bytes(int64_t n, int total_bits);
+size_t compact_workspace_bytes(int64_t n);
+// Sorts lookups by `key`; on return *perm_out points into ws at the
+// permutation (sorted position -> input index).
+hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
+                       const int32_t* mat, const uint8_t* active, void* ws,
+                       const int32_t** perm_out, hipStream_t s);
+// Stable compaction of active slots: perm (in ws) lists them in input
+// order, *count_out (device) their number.
+hipError_t launch_compact(int64_t n, const uint8_t* active, void* ws,
+                          const int32_t** perm_out,
+                          const int64_t** count_out, hipStream_t s);
+
+}  // namespace xs

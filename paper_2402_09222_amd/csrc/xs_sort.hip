@@ -1,0 +1,361 @@
+// Queue formation: stable LSD radix sort of lookups by (material, energy)
+// and stable compaction of active slots.
+//
+// The paper (section 5.1, "minimum sorting threshold") sorts particles so
+// that neighbours in the buffer sit in the same material and near in energy,
+// improving the locality of the cross-section lookup; the order never changes
+// a lookup's value.  Here the key is a 32-bit word: an optional inactive
+// flag, the material, and the top bits of the energy's IEEE pattern above
+// the table's lowest energy (monotone in E for positive doubles).  Each
+// 8-bit digit pass is reduce-then-scan: per-tile digit histograms, a scan to
+// global offsets, then a scatter whose ranks inside a 64-lane wave come from
+// ballots (lanes holding the same digit find each other with 8 ballots).
+#include "xs_internal.h"
+
+namespace xs {
+
+namespace {
+
+struct SortSrc {
+  const double* E;
+  const int32_t* mat;
+  const uint8_t* active;
+  SortKey key;
+  int64_t n;
+};
+
+__device__ __forceinline__ uint32_t make_key(const SortKey& k, double e,
+                                             int32_t m, bool inactive) {
+  uint32_t key = 0;
+  if (k.e_bits) {
+    int64_t d = __double_as_longlong(e) - k.e_bits_min;
+    d = d < 0 ? 0 : (d >> k.e_shift);
+    const int64_t maxv = (1ll << k.e_bits) - 1;
+    key = (uint32_t)(d > maxv ? maxv : d);
+  }
+  if (k.mat_bits) {
+    const int32_t mm = m < 0 ? 0 : (m >= k.M ? k.M - 1 : m);
+    key |= (uint32_t)mm << k.e_bits;
+  }
+  if (k.flag_bit && inactive) key |= 1u << (k.mat_bits + k.e_bits);
+  return key;
+}
+
+__device__ __forceinline__ uint32_t src_key(const SortSrc& s, int64_t i) {
+  return make_key(s.key, s.E[i], s.mat[i], s.active && !s.active[i]);
+}
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Inclusive scan over a 64-lane wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Inclusive scan over a block of NT threads; *total gets the block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t x,
+                                                    uint32_t* total) {
+  __shared__ uint32_t wsum[NT / 64];
+  const uint32_t incl = wave_incl_scan(x);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const uint32_t s = wsum[i];
+    off += i < w ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return incl + off;
+}
+
+// Per-tile digit histogram, digit-major: hist[d * nT + tile].
+template <bool FROM_INPUT>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
+    SortSrc src, const uint32_t* __restrict__ keys_in, int shift,
+    uint32_t* __restrict__ hist, int32_t nT) {
+  __shared__ uint32_t h[kRadixBins];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * kSortThreads + tid;
+    if (i < src.n) {
+      const uint32_t key = FROM_INPUT ? src_key(src, i) : keys_in[i];
+      atomicAdd(&h[(key >> shift) & (kRadixBins - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)tid * nT + blockIdx.x] = h[tid];
+}
+
+// totals[d] = sum of row d.
+__global__ __launch_bounds__(256) void k_digit_totals(
+    const uint32_t* __restrict__ hist, int32_t nT, uint32_t* __restrict__ totals) {
+  const uint32_t* row = hist + (int64_t)blockIdx.x * nT;
+  uint32_t s = 0;
+  for (int i = threadIdx.x; i < nT; i += 256) s += row[i];
+  uint32_t tot;
+  block_incl_scan<256>(s, &tot);
+  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+}
+
+// Row d becomes its exclusive scan plus the count of all smaller digits:
+// hist[d * nT + tile] = first output position of digit d from that tile.
+__global__ __launch_bounds__(256) void k_row_scan(
+    uint32_t* __restrict__ hist, int32_t nT, const uint32_t* __restrict__ totals) {
+  const int d = blockIdx.x;
+  uint32_t base;
+  block_incl_scan<256>(threadIdx.x < (unsigned)d ? totals[threadIdx.x] : 0u,
+                       &base);
+  uint32_t* row = hist + (int64_t)d * nT;
+  uint32_t carry = base;
+  for (int c0 = 0; c0 < nT; c0 += 256) {
+    const int i = c0 + threadIdx.x;
+    const uint32_t x = i < nT ? row[i] : 0u;
+    uint32_t tot;
+    const uint32_t incl = block_incl_scan<256>(x, &tot);
+    if (i < nT) row[i] = carry + incl - x;
+    carry += tot;
+  }
+}
+
+// Stable scatter of one digit pass.  Wave w of the block owns the tile's
+// elements [w*1024, (w+1)*1024), read 64 at a time in order, so the order
+// (wave, round, lane) is input order.  wcnt[w][d] counts digit d so far in
+// wave w; after the rounds the waves' counts are prefixed per digit.
+template <bool FROM_INPUT, bool WRITE_KEYS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    SortSrc src, const uint32_t* __restrict__ keys_in,
+    const uint32_t* __restrict__ vals_in, int shift,
+    const uint32_t* __restrict__ offs, int32_t nT,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  constexpr int kWaves = kSortThreads / 64;
+  constexpr int kPerWave = kSortTile / kWaves;
+  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < kWaves * kRadixBins; i += kSortThreads)
+    (&wcnt[0][0])[i] = 0;
+  const uint32_t tile_off = offs[(int64_t)tid * nT + blockIdx.x];
+  __syncthreads();
+
+  const uint64_t below = lanes_below(lane);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + w * kPerWave;
+  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    const bool ok = i < src.n;
+    uint32_t k = 0, v = 0;
+    if (ok) {
+      if (FROM_INPUT) {
+        k = src_key(src, i);
+        v = (uint32_t)i;
+      } else {
+        k = keys_in[i];
+        v = vals_in[i];
+      }
+    }
+    const uint32_t d = (k >> shift) & (kRadixBins - 1);
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t before = wcnt[w][d];
+    rank[r] = before + (uint32_t)__popcll(peers & below);
+    if (ok && (peers & below) == 0)
+      wcnt[w][d] = before + (uint32_t)__popcll(peers);
+    key[r] = k;
+    val[r] = v;
+  }
+  __syncthreads();
+  {
+    uint32_t s = tile_off;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) {
+      const uint32_t c = wcnt[ww][tid];
+      wcnt[ww][tid] = s;
+      s += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    if (i < src.n) {
+      const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
+      const uint32_t pos = wcnt[w][d] + rank[r];
+      if (pos < (uint64_t)src.n) {  // always true when offsets are consistent
+        if (WRITE_KEYS) keys_out[pos] = key[r];
+        vals_out[pos] = val[r];
+      }
+    }
+  }
+}
+
+// ---- compaction ----------------------------------------------------------
+
+__global__ __launch_bounds__(kSortThreads) void k_compact_count(
+    const uint8_t* __restrict__ active, int64_t n, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t wtot[kSortThreads / 64];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + w * (kSortTile / 4);
+  uint32_t c = 0;
+#pragma unroll 4
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    c += (uint32_t)__popcll(__ballot(i < n && active[i] != 0));
+  }
+  if (lane == 0) wtot[w] = c;
+  __syncthreads();
+  if (tid == 0) cnt[blockIdx.x] = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+}
+
+// Exclusive scan of the tile counts in one block; total -> *count.
+__global__ __launch_bounds__(1024) void k_compact_scan(
+    uint32_t* __restrict__ cnt, int32_t nT, int64_t* __restrict__ count) {
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < nT; c0 += 1024) {
+    const int i = c0 + threadIdx.x;
+    const uint32_t x = i < nT ? cnt[i] : 0u;
+    uint32_t tot;
+    const uint32_t incl = block_incl_scan<1024>(x, &tot);
+    if (i < nT) cnt[i] = carry + incl - x;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_compact_scatter(
+    const uint8_t* __restrict__ active, int64_t n,
+    const uint32_t* __restrict__ toff, int32_t* __restrict__ list) {
+  __shared__ uint32_t wtot[kSortThreads / 64];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + w * (kSortTile / 4);
+  uint64_t bal[kSortItems];
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    bal[r] = __ballot(i < n && active[i] != 0);
+    c += (uint32_t)__popcll(bal[r]);
+  }
+  if (lane == 0) wtot[w] = c;
+  __syncthreads();
+  uint32_t pos = toff[blockIdx.x];
+  for (int ww = 0; ww < w; ++ww) pos += wtot[ww];
+  const uint64_t below = lanes_below(lane);
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t at = pos + (uint32_t)__popcll(bal[r] & below);
+    if (((bal[r] >> lane) & 1ull) && at < (uint64_t)n)
+      list[at] = (int32_t)(base + r * 64 + lane);
+    pos += (uint32_t)__popcll(bal[r]);
+  }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+size_t sort_workspace_bytes(int64_t n, int total_bits) {
+  (void)total_bits;
+  const int64_t nT = (n + kSortTile - 1) / kSortTile;
+  return 4 * align256((size_t)n * 4) + align256((size_t)nT * kRadixBins * 4) +
+         align256(kRadixBins * 4);
+}
+
+size_t compact_workspace_bytes(int64_t n) {
+  const int64_t nT = (n + kSortTile - 1) / kSortTile;
+  return align256((size_t)n * 4) + align256((size_t)nT * 4) + align256(8);
+}
+
+hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
+                       const int32_t* mat, const uint8_t* active, void* ws,
+                       const int32_t** perm_out, hipStream_t s) {
+  const int32_t nT = (int32_t)((n + kSortTile - 1) / kSortTile);
+  char* p = (char*)ws;
+  uint32_t* bufk[2];
+  uint32_t* bufv[2];
+  bufk[0] = (uint32_t*)p; p += align256((size_t)n * 4);
+  bufv[0] = (uint32_t*)p; p += align256((size_t)n * 4);
+  bufk[1] = (uint32_t*)p; p += align256((size_t)n * 4);
+  bufv[1] = (uint32_t*)p; p += align256((size_t)n * 4);
+  uint32_t* hist = (uint32_t*)p; p += align256((size_t)nT * kRadixBins * 4);
+  uint32_t* totals = (uint32_t*)p;
+
+  SortSrc src{E, mat, active, key, n};
+  const int passes = (key.total_bits + kRadixBits - 1) / kRadixBits;
+  int cur = 0;  // buffer holding the current keys/vals (after pass 0)
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = pass * kRadixBits;
+    const bool first = pass == 0, last = pass == passes - 1;
+    const int dst = first ? 0 : 1 - cur;
+    if (first)
+      hipLaunchKernelGGL((k_radix_hist<true>), dim3(nT), dim3(kSortThreads), 0,
+                         s, src, nullptr, shift, hist, nT);
+    else
+      hipLaunchKernelGGL((k_radix_hist<false>), dim3(nT), dim3(kSortThreads), 0,
+                         s, src, bufk[cur], shift, hist, nT);
+    hipLaunchKernelGGL(k_digit_totals, dim3(kRadixBins), dim3(256), 0, s, hist,
+                       nT, totals);
+    hipLaunchKernelGGL(k_row_scan, dim3(kRadixBins), dim3(256), 0, s, hist, nT,
+                       totals);
+    if (first && last)
+      hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(nT),
+                         dim3(kSortThreads), 0, s, src, nullptr, nullptr, shift,
+                         hist, nT, bufk[dst], bufv[dst]);
+    else if (first)
+      hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3(nT),
+                         dim3(kSortThreads), 0, s, src, nullptr, nullptr, shift,
+                         hist, nT, bufk[dst], bufv[dst]);
+    else if (last)
+      hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(nT),
+                         dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
+                         shift, hist, nT, bufk[dst], bufv[dst]);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(nT),
+                         dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
+                         shift, hist, nT, bufk[dst], bufv[dst]);
+    cur = dst;
+  }
+  *perm_out = (const int32_t*)bufv[cur];
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(int64_t n, const uint8_t* active, void* ws,
+                          const int32_t** perm_out, const int64_t** count_out,
+                          hipStream_t s) {
+  const int32_t nT = (int32_t)((n + kSortTile - 1) / kSortTile);
+  char* p = (char*)ws;
+  int32_t* list = (int32_t*)p; p += align256((size_t)n * 4);
+  uint32_t* cnt = (uint32_t*)p; p += align256((size_t)nT * 4);
+  int64_t* count = (int64_t*)p;
+  hipLaunchKernelGGL(k_compact_count, dim3(nT), dim3(kSortThreads), 0, s,
+                     active, n, cnt);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, cnt, nT, count);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nT), dim3(kSortThreads), 0, s,
+                     active, n, cnt, list);
+  *perm_out = list;
+  *count_out = count;
+  return hipGetLastError();
+}
+
+}  // namespace xs

@@ -1,0 +1,389 @@
+"""ctypes binding of libxs.so with the same names as include/xs.h.
+
+Argument marshalling only: every step of a lookup runs in the library's HIP
+kernels.  torch supplies device memory (output and workspace tensors) and the
+HIP stream (torch.cuda.current_stream()).  If libxs.so has not been built the
+first call raises; nothing here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxs.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "xs.h")
+
+XS_OK, XS_EINVAL, XS_ETABLE, XS_ENOTBUILT = 0, -1, -2, -3
+XS_EWORKSPACE, XS_ENOMEM, XS_EHIP, XS_ETIMEOUT = -4, -5, -6, -7
+XS_AUTO = -1
+XS_CHANNELS = 5
+XS_GRID_NUCLIDE, XS_GRID_HASH, XS_GRID_UNIONIZED = 0, 1, 2
+XS_FP64, XS_FP32 = 0, 1
+XS_SORT_NONE, XS_SORT_MATERIAL, XS_SORT_ENERGY, XS_SORT_MATERIAL_ENERGY = 0, 1, 2, 3
+XS_QUEUE_COMPACT, XS_QUEUE_PREDICATED = 0, 1
+XS_BUILD_FP32, XS_BUILD_HASH, XS_BUILD_UNIONIZED = 1, 2, 4
+INT64_MAX = (1 << 63) - 1
+
+GRIDS = {"nuclide": XS_GRID_NUCLIDE, "hash": XS_GRID_HASH,
+         "unionized": XS_GRID_UNIONIZED}
+SORTS = {"none": XS_SORT_NONE, "material": XS_SORT_MATERIAL,
+         "energy": XS_SORT_ENERGY, "material_energy": XS_SORT_MATERIAL_ENERGY}
+
+
+class XsError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {message} (status {status})")
+        self.status = status
+
+
+class xs_table_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_nuclides", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("grid_offsets", ctypes.c_void_p),
+        ("energy", ctypes.c_void_p),
+        ("xs", ctypes.c_void_p),
+        ("n_materials", ctypes.c_int32),
+        ("mat_offsets", ctypes.c_void_p),
+        ("mat_nuclides", ctypes.c_void_p),
+        ("mat_density", ctypes.c_void_p),
+        ("build_flags", ctypes.c_uint32),
+        ("n_hash_bins", ctypes.c_int32),
+    ]
+
+
+class xs_params(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("sort", ctypes.c_int32),
+        ("block_size", ctypes.c_int32),
+        ("lookups_per_thread", ctypes.c_int32),
+        ("lds_stage", ctypes.c_int32),
+        ("sort_threshold", ctypes.c_int64),
+        ("queue", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class xs_table_info_t(ctypes.Structure):
+    _fields_ = [
+        ("n_nuclides", ctypes.c_int32),
+        ("n_materials", ctypes.c_int32),
+        ("max_material_size", ctypes.c_int32),
+        ("n_hash_bins", ctypes.c_int32),
+        ("n_points", ctypes.c_int64),
+        ("union_size", ctypes.c_int64),
+        ("build_flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("e_min", ctypes.c_double),
+        ("e_max", ctypes.c_double),
+        ("bytes_grid", ctypes.c_size_t),
+        ("bytes_fp64", ctypes.c_size_t),
+        ("bytes_fp32", ctypes.c_size_t),
+        ("bytes_materials", ctypes.c_size_t),
+        ("bytes_hash", ctypes.c_size_t),
+        ("bytes_union", ctypes.c_size_t),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class xs_profile_t(ctypes.Structure):
+    _fields_ = [
+        ("ms_sort", ctypes.c_double),
+        ("ms_lookup", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+        ("calls", ctypes.c_int64),
+        ("sorted_calls", ctypes.c_int64),
+        ("lookups", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def declared_functions() -> list:
+    """Names of the functions include/xs.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xs_[a-z_0-9]+)\s*\(", text)))
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libxs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with __graft_entry__.build() or "
+            "python paper_2402_09222_amd/build.py")
+    lib = ctypes.CDLL(path)
+    i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "xs_create_tables": ([P(xs_table_desc), vp, P(vp)], i32),
+        "xs_destroy_tables": ([vp], i32),
+        "xs_table_info": ([vp, P(xs_table_info_t)], i32),
+        "xs_params_default": ([P(xs_params), i32], i32),
+        "xs_resolve_params": ([vp, i64, P(xs_params), P(xs_params)], i32),
+        "xs_workspace_size": ([vp, i64, P(xs_params), P(sz)], i32),
+        "xs_lookup_batch": ([vp, i64, vp, vp, vp, P(xs_params), vp, sz, vp], i32),
+        "xs_lookup_active": ([vp, i64, vp, vp, vp, vp, P(xs_params), vp, sz, vp],
+                             i32),
+        "xs_lookup_indices": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
+        "xs_profile_begin": ([vp], i32),
+        "xs_profile_end": ([vp, P(xs_profile_t)], i32),
+        "xs_status_string": ([i32], ctypes.c_char_p),
+        "xs_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != XS_OK:
+        lib = load_library()
+        msg = lib.xs_last_error().decode() or lib.xs_status_string(status).decode()
+        raise XsError(status, where, msg)
+
+
+def xs_status_string(status: int) -> str:
+    return load_library().xs_status_string(status).decode()
+
+
+def xs_last_error() -> str:
+    return load_library().xs_last_error().decode()
+
+
+def _stream_ptr(stream, device=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_params(precision=XS_FP64, grid=XS_AUTO, sort=XS_AUTO, block_size=0,
+                lookups_per_thread=0, lds_stage=XS_AUTO, sort_threshold=-1,
+                queue=XS_AUTO) -> xs_params:
+    if isinstance(grid, str):
+        grid = GRIDS[grid]
+    if isinstance(sort, str):
+        sort = SORTS[sort]
+    return xs_params(precision, grid, sort, block_size, lookups_per_thread,
+                     lds_stage, sort_threshold, queue, 0)
+
+
+class Tables:
+    """Owns an xs_tables_t handle (freed by close() or garbage collection)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self.handle = handle
+
+    def close(self):
+        if self.handle and self.handle.value:
+            _check(load_library().xs_destroy_tables(self.handle),
+                   "xs_destroy_tables")
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def make_desc(t, build_flags: int = 0, n_hash_bins: int = 0):
+    """xs_table_desc over host numpy arrays of a table set (any object with
+    grid_offsets, energy, xs, mat_offsets, mat_nuclides, mat_density).
+    Returns (desc, keep) where keep holds the arrays alive."""
+    import numpy as np
+    keep = dict(
+        grid_offsets=np.ascontiguousarray(t.grid_offsets, dtype=np.int64),
+        energy=np.ascontiguousarray(t.energy, dtype=np.float64),
+        xs=np.ascontiguousarray(t.xs, dtype=np.float64).reshape(-1),
+        mat_offsets=np.ascontiguousarray(t.mat_offsets, dtype=np.int32),
+        mat_nuclides=np.ascontiguousarray(t.mat_nuclides, dtype=np.int32),
+        mat_density=np.ascontiguousarray(t.mat_density, dtype=np.float64),
+    )
+    d = xs_table_desc(
+        len(keep["grid_offsets"]) - 1, XS_CHANNELS,
+        keep["grid_offsets"].ctypes.data, keep["energy"].ctypes.data,
+        keep["xs"].ctypes.data, len(keep["mat_offsets"]) - 1,
+        keep["mat_offsets"].ctypes.data, keep["mat_nuclides"].ctypes.data,
+        keep["mat_density"].ctypes.data, build_flags, n_hash_bins)
+    return d, keep
+
+
+def xs_create_tables(t, build_flags: int = XS_BUILD_FP32 | XS_BUILD_HASH,
+                     n_hash_bins: int = 4000, stream=None) -> Tables:
+    """Upload a table set (see make_desc) and build the requested structures.
+    The paper's default bin count is 4,000."""
+    lib = load_library()
+    desc, keep = make_desc(t, build_flags, n_hash_bins)
+    h = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+    _check(lib.xs_create_tables(ctypes.byref(desc), s, ctypes.byref(h)),
+           "xs_create_tables")
+    del keep
+    return Tables(h)
+
+
+def xs_destroy_tables(tables: Tables):
+    tables.close()
+
+
+def xs_table_info(tables: Tables) -> dict:
+    info = xs_table_info_t()
+    _check(load_library().xs_table_info(tables.handle, ctypes.byref(info)),
+           "xs_table_info")
+    return info.as_dict()
+
+
+def xs_params_default(precision: int = XS_FP64) -> xs_params:
+    p = xs_params()
+    _check(load_library().xs_params_default(ctypes.byref(p), precision),
+           "xs_params_default")
+    return p
+
+
+def xs_resolve_params(tables: Tables, n: int, params: xs_params = None) -> xs_params:
+    out = xs_params()
+    _check(load_library().xs_resolve_params(
+        tables.handle, n, ctypes.byref(params) if params is not None else None,
+        ctypes.byref(out)), "xs_resolve_params")
+    return out
+
+
+def xs_workspace_size(tables: Tables, n: int, params: xs_params = None) -> int:
+    b = ctypes.c_size_t()
+    _check(load_library().xs_workspace_size(
+        tables.handle, n, ctypes.byref(params) if params is not None else None,
+        ctypes.byref(b)), "xs_workspace_size")
+    return b.value
+
+
+def _workspace(nbytes: int, device):
+    """A 256-byte aligned device buffer of nbytes (torch uint8 tensor, ptr)."""
+    import torch
+    if nbytes == 0:
+        return None, None, 0
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = buf.data_ptr()
+    off = (-ptr) % 256
+    return buf, ctypes.c_void_p(ptr + off), nbytes
+
+
+def _out_tensor(n, params, device, out):
+    import torch
+    prec = params.precision if params is not None else XS_FP64
+    dt = torch.float64 if prec == XS_FP64 else torch.float32
+    if out is None:
+        return torch.empty((n, XS_CHANNELS), dtype=dt, device=device)
+    if out.dtype != dt or out.shape[0] < n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [n, 5] tensor of the "
+                         "precision's dtype")
+    return out
+
+
+def _check_queries(E, mat):
+    import torch
+    if E.dtype != torch.float64 or mat.dtype != torch.int32:
+        raise TypeError("E must be float64 and mat int32")
+    if not (E.is_cuda and mat.is_cuda):
+        raise TypeError("E and mat must be device tensors")
+    if not (E.is_contiguous() and mat.is_contiguous()) or E.numel() != mat.numel():
+        raise ValueError("E and mat must be contiguous and of equal length")
+
+
+def xs_lookup_batch(tables: Tables, E, mat, out=None, params: xs_params = None,
+                    workspace=None, stream=None):
+    """out[q, c] = macroscopic value of channel c for (E[q], mat[q]).
+    E: float64 device tensor [n]; mat: int32 device tensor [n].  Returns out
+    ([n, 5], float64 for XS_FP64, float32 for XS_FP32)."""
+    _check_queries(E, mat)
+    n = E.numel()
+    out = _out_tensor(n, params, E.device, out)
+    pp = ctypes.byref(params) if params is not None else None
+    if workspace is None:
+        nb = xs_workspace_size(tables, n, params)
+        keep, ws, nb = _workspace(nb, E.device)
+    else:
+        keep, ws, nb = workspace
+    _check(load_library().xs_lookup_batch(
+        tables.handle, n, ctypes.c_void_p(E.data_ptr()),
+        ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(out.data_ptr()), pp,
+        ws, nb, _stream_ptr(stream, E.device)), "xs_lookup_batch")
+    return out
+
+
+def xs_lookup_active(tables: Tables, E, mat, active, out, params: xs_params = None,
+                     workspace=None, stream=None):
+    """As xs_lookup_batch for slots with active[q] != 0 (uint8 device
+    tensor); other rows of `out` are left as they were."""
+    import torch
+    _check_queries(E, mat)
+    if active.dtype != torch.uint8 or active.numel() != E.numel():
+        raise TypeError("active must be a uint8 tensor of length n")
+    n = E.numel()
+    out = _out_tensor(n, params, E.device, out)
+    pp = ctypes.byref(params) if params is not None else None
+    if workspace is None:
+        nb = xs_workspace_size(tables, n, params)
+        keep, ws, nb = _workspace(nb, E.device)
+    else:
+        keep, ws, nb = workspace
+    _check(load_library().xs_lookup_active(
+        tables.handle, n, ctypes.c_void_p(E.data_ptr()),
+        ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(active.data_ptr()),
+        ctypes.c_void_p(out.data_ptr()), pp, ws, nb,
+        _stream_ptr(stream, E.device)), "xs_lookup_active")
+    return out
+
+
+def xs_lookup_indices(tables: Tables, E, mat, idx_offsets, grid=XS_GRID_NUCLIDE,
+                      idx=None, stream=None):
+    """Brackets of every (lookup, nuclide) pair with the given grid method.
+    idx_offsets: int64 device tensor [n+1].  Returns idx (int32 [total])."""
+    import torch
+    _check_queries(E, mat)
+    if isinstance(grid, str):
+        grid = GRIDS[grid]
+    total = int(idx_offsets[-1].item()) if idx_offsets.numel() else 0
+    if idx is None:
+        idx = torch.full((max(total, 1),), -2, dtype=torch.int32, device=E.device)
+    _check(load_library().xs_lookup_indices(
+        tables.handle, E.numel(), ctypes.c_void_p(E.data_ptr()),
+        ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(idx_offsets.data_ptr()),
+        ctypes.c_void_p(idx.data_ptr()), grid, _stream_ptr(stream, E.device)),
+        "xs_lookup_indices")
+    return idx[:total]
+
+
+def xs_profile_begin(tables: Tables):
+    _check(load_library().xs_profile_begin(tables.handle), "xs_profile_begin")
+
+
+def xs_profile_end(tables: Tables) -> dict:
+    p = xs_profile_t()
+    _check(load_library().xs_profile_end(tables.handle, ctypes.byref(p)),
+           "xs_profile_end")
+    return p.as_dict()

@@ -1,0 +1,175 @@
+"""The C interface without a GPU: the library loads, exports every function
+include/xs.h declares, its structs match the binding's layouts, and host-side
+validation rejects bad tables and arguments before any device call."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2402_09222_amd import xs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(xs.LIB_PATH):
+        from paper_2402_09222_amd import build
+        build.build()
+    return xs.load_library()
+
+
+def test_exports_every_declared_function(lib):
+    names = xs.declared_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", xs.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    assert set(names) <= exported
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "xs.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(xs_table_desc), sizeof(xs_params),
+         sizeof(xs_table_info_t), sizeof(xs_profile_t));
+  printf("%zu %zu %zu\n", offsetof(xs_table_desc, n_hash_bins),
+         offsetof(xs_params, sort_threshold), offsetof(xs_table_info_t, e_min));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"),
+                    "-o", str(exe), str(src)], check=True)
+    sizes, offs = subprocess.run([str(exe)], capture_output=True, text=True,
+                                 check=True).stdout.split("\n")[:2]
+    assert [int(v) for v in sizes.split()] == [
+        ctypes.sizeof(xs.xs_table_desc), ctypes.sizeof(xs.xs_params),
+        ctypes.sizeof(xs.xs_table_info_t), ctypes.sizeof(xs.xs_profile_t)]
+    assert [int(v) for v in offs.split()] == [
+        xs.xs_table_desc.n_hash_bins.offset, xs.xs_params.sort_threshold.offset,
+        xs.xs_table_info_t.e_min.offset]
+
+
+def test_status_strings(lib):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert xs.xs_status_string(st).startswith("XS_")
+    assert "unknown" in xs.xs_status_string(-99)
+
+
+def test_params_default(lib):
+    p = xs.xs_params_default(xs.XS_FP32)
+    assert p.precision == xs.XS_FP32
+    assert p.grid == xs.XS_AUTO and p.sort == xs.XS_AUTO
+    assert p.block_size == 0 and p.lookups_per_thread == 0
+    assert p.sort_threshold == -1 and p.reserved == 0
+    with pytest.raises(xs.XsError) as e:
+        xs.xs_params_default(7)
+    assert e.value.status == xs.XS_EINVAL
+
+
+def _small():
+    return synth.random_tables(5, 3, [4, 5, 6], 2, sizes=[2, 3])
+
+
+def _create_status(t, flags=0, bins=0, **over):
+    desc, keep = xs.make_desc(t, flags, bins)
+    for k, v in over.items():
+        setattr(desc, k, v)
+    h = ctypes.c_void_p()
+    st = xs.load_library().xs_create_tables(ctypes.byref(desc), None,
+                                            ctypes.byref(h))
+    return st, xs.xs_last_error(), h
+
+
+def _mutated(**arrays):
+    t = _small()
+    d = dict(grid_offsets=t.grid_offsets.copy(), energy=t.energy.copy(),
+             xs=t.xs.copy(), mat_offsets=t.mat_offsets.copy(),
+             mat_nuclides=t.mat_nuclides.copy(), mat_density=t.mat_density.copy())
+    for k, fn in arrays.items():
+        fn(d[k])
+    return synth.Tables(**d)
+
+
+def _set(i, v):
+    def f(a):
+        a.reshape(-1)[i] = v
+    return f
+
+
+BAD_TABLES = {
+    "energy_not_increasing": dict(energy=_set(1, 1e-5)),
+    "energy_nan": dict(energy=_set(2, np.nan)),
+    "energy_negative": dict(energy=_set(0, -1.0)),
+    "energy_zero": dict(energy=_set(0, 0.0)),
+    "xs_negative": dict(xs=_set(7, -0.5)),
+    "xs_inf": dict(xs=_set(3, np.inf)),
+    "density_zero": dict(mat_density=_set(0, 0.0)),
+    "density_nan": dict(mat_density=_set(1, np.nan)),
+    "nuclide_out_of_range": dict(mat_nuclides=_set(0, 3)),
+    "nuclide_negative": dict(mat_nuclides=_set(1, -1)),
+    "offset_start": dict(grid_offsets=_set(0, 1)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BAD_TABLES))
+def test_create_rejects_bad_tables(lib, name):
+    st, msg, h = _create_status(_mutated(**BAD_TABLES[name]))
+    assert st == xs.XS_ETABLE, (st, msg)
+    assert msg
+    assert not h.value
+
+
+def test_create_rejects_structure(lib):
+    t = _small()
+    assert _create_status(t, n_channels=4)[0] == xs.XS_ETABLE
+    assert _create_status(t, n_nuclides=0)[0] == xs.XS_ETABLE
+    assert _create_status(t, n_materials=0)[0] == xs.XS_ETABLE
+    assert _create_status(t, flags=8)[0] == xs.XS_EINVAL
+    assert _create_status(t, flags=xs.XS_BUILD_HASH, bins=0)[0] == xs.XS_EINVAL
+    assert _create_status(t, flags=xs.XS_BUILD_HASH, bins=100001)[0] == xs.XS_EINVAL
+    # a nuclide with a single grid point
+    one = synth.Tables(np.array([0, 1, 3], np.int64), np.array([0.5, 0.1, 0.9]),
+                       np.ones((3, 5)), np.array([0, 1], np.int32),
+                       np.array([0], np.int32), np.array([1.0]))
+    assert _create_status(one)[0] == xs.XS_ETABLE
+    # an empty material and a repeated nuclide
+    t2 = synth.Tables(t.grid_offsets, t.energy, t.xs, np.array([0, 0, 2], np.int32),
+                      np.array([0, 1], np.int32), np.array([1.0, 1.0]))
+    assert _create_status(t2)[0] == xs.XS_ETABLE
+    t3 = synth.Tables(t.grid_offsets, t.energy, t.xs, np.array([0, 2], np.int32),
+                      np.array([1, 1], np.int32), np.array([1.0, 1.0]))
+    assert _create_status(t3)[0] == xs.XS_ETABLE
+
+
+def test_null_arguments(lib):
+    h = ctypes.c_void_p()
+    assert lib.xs_create_tables(None, None, ctypes.byref(h)) == xs.XS_EINVAL
+    assert lib.xs_destroy_tables(None) == xs.XS_OK
+    assert lib.xs_lookup_batch(None, 10, None, None, None, None, None, 0,
+                               None) == xs.XS_EINVAL
+    assert lib.xs_lookup_indices(None, 1, None, None, None, None, 0,
+                                 None) == xs.XS_EINVAL
+    info = xs.xs_table_info_t()
+    assert lib.xs_table_info(None, ctypes.byref(info)) == xs.XS_EINVAL
+    assert lib.xs_profile_begin(None) == xs.XS_EINVAL
+
+
+def test_valid_tables_pass_validation(lib):
+    """A valid description gets past every host check; without a device the
+    first HIP call is what fails."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present; covered by the GPU tests")
+    st, msg, h = _create_status(_small(), xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH, 100)
+    assert st == xs.XS_EHIP, (st, msg)

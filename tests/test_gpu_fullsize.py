@@ -1,0 +1,127 @@
+"""Full-size synthetic workload (355 nuclides x 11,303 points, 12 materials,
+10M lookups) in the launch shapes the benchmark times.
+
+The oracle computes sampled lookups one by one; the whole output is checked
+through properties that hold at any size: every grid method, sort policy and
+launch shape gives bit-identical sums within one precision, and the FP32 form
+stays within 2e-6 of the FP64 result everywhere.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2402_09222_amd import xs  # noqa: E402
+
+N = 10_000_000
+SAMPLES = 20_000
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full():
+    say("full size: generating tables and 10M queries")
+    t = synth.config2_tables()
+    q = synth.config2_queries(N)
+    flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED
+    say("full size: building tables (hash 8192 bins, unionized grid)")
+    h = xs.xs_create_tables(t, flags, 8192)
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    s = synth.Stream(41, 1)
+    pick = np.unique(np.concatenate([
+        s.integers(SAMPLES, 0, N - 1), np.arange(64), np.arange(N - 64, N)]))
+    ref = oracle.lookup(t, q.E[pick], q.mat[pick], threads=8)
+    ref32 = oracle.lookup_f32(t, q.E[pick], q.mat[pick], threads=8)
+    yield dict(t=t, q=q, h=h, E=E, m=m, pick=pick, ref=ref, ref32=ref32)
+    h.close()
+
+
+def run(f, n=N, **kw):
+    p = xs.make_params(**kw)
+    out = xs.xs_lookup_batch(f["h"], f["E"][:n], f["m"][:n], params=p)
+    torch.cuda.synchronize()
+    return out
+
+
+PLAIN = dict(precision=xs.XS_FP64, grid="nuclide", sort="none", block_size=256,
+             lookups_per_thread=1)
+
+
+def test_plain_fp64_samples(full):
+    say("plain fp64 full size")
+    out = run(full, **PLAIN).cpu().numpy()
+    got = out[full["pick"]]
+    assert (np.abs(got - full["ref"]) / full["ref"]).max() <= 1e-12
+    assert np.array_equal(got, full["ref"])
+    assert np.all(np.isfinite(out)) and np.all(out > 0)
+    full["out64"] = torch.from_numpy(out)
+
+
+@pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
+@pytest.mark.parametrize("sort", ["none", "material", "energy", "material_energy"])
+def test_fp64_grids_and_sorts_identical(full, grid, sort):
+    say("fp64 full size", grid, sort)
+    if "out64" not in full:
+        pytest.skip("plain run failed")
+    out = run(full, precision=xs.XS_FP64, grid=grid, sort=sort,
+              sort_threshold=0, block_size=256, lookups_per_thread=2)
+    assert torch.equal(out.cpu(), full["out64"])
+
+
+@pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
+def test_fp32_samples_and_bound(full, grid):
+    say("fp32 full size", grid)
+    out = run(full, precision=xs.XS_FP32, grid=grid, sort="material_energy",
+              sort_threshold=20000, block_size=256, lookups_per_thread=2)
+    o = out.cpu().numpy()
+    assert np.array_equal(o[full["pick"]], full["ref32"])
+    if "out64" in full:
+        ref = full["out64"].numpy()
+        rel = np.abs(o.astype(np.float64) - ref) / ref
+        say("fp32 rel err per channel max", rel.max(axis=0), "mean",
+            rel.mean(axis=0))
+        assert rel.max() <= 2e-6
+    for k in (dict(sort="none", block_size=1024, lookups_per_thread=1),
+              dict(sort="material", sort_threshold=0, block_size=512,
+                   lookups_per_thread=4)):
+        o2 = run(full, precision=xs.XS_FP32, grid=grid, **k).cpu().numpy()
+        assert np.array_equal(o2, o), k
+
+
+def test_ragged_batch(full):
+    n = N - 9
+    say("ragged", n)
+    out = run(full, n=n, precision=xs.XS_FP64, grid="hash",
+              sort="material_energy", sort_threshold=0, block_size=192,
+              lookups_per_thread=3)
+    if "out64" in full:
+        assert torch.equal(out.cpu(), full["out64"][:n])
+
+
+@pytest.mark.parametrize("grid", ["hash", "unionized"])
+def test_indices_match_bisection(full, grid):
+    n = 1_000_000
+    say("indices full tables", grid)
+    t, q = full["t"], full["q"]
+    off = oracle.index_offsets(t, q.mat[:n])
+    offd = torch.from_numpy(off).to("cuda:0")
+    a = xs.xs_lookup_indices(full["h"], full["E"][:n], full["m"][:n], offd,
+                             grid="nuclide")
+    b = xs.xs_lookup_indices(full["h"], full["E"][:n], full["m"][:n], offd,
+                             grid=grid)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    _, idx_ref, off_s = oracle.lookup(t, q.E[:2000], q.mat[:2000],
+                                      with_index=True)
+    assert np.array_equal(a[:off_s[-1]].cpu().numpy(), idx_ref)

@@ -1,0 +1,275 @@
+"""HIP lookup against the CPU oracle, through the C interface.
+
+Bars (fixed here, from the requirements of the lookup):
+  * brackets: bit-exact for every grid method;
+  * FP64 sums: <= 1e-12 relative per channel, and in fact bit-identical
+    (same operations in the same order, correctly rounded division, no fused
+    multiply-add on either side);
+  * FP32 form: bit-identical to the oracle's FP32 form and <= 2e-6 relative to
+    the FP64 oracle per channel;
+  * sort policy, threshold, block size and lookups per thread never change a
+    single bit of the output.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2402_09222_amd import xs  # noqa: E402
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-6
+ALL_FLAGS = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dtype,
+                                                       device="cuda:0")
+
+
+def run(tables, E, m, **kw):
+    prec = kw.pop("precision", xs.XS_FP64)
+    p = xs.make_params(precision=prec, **kw)
+    out = xs.xs_lookup_batch(tables, E, m, params=p)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def rel_err(got, ref):
+    return np.abs(got.astype(np.float64) - ref) / np.abs(ref)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    t = synth.config1_tables()
+    q = synth.config1_queries()
+    say("cfg1: building tables (all structures, 4000 hash bins)")
+    h = xs.xs_create_tables(t, ALL_FLAGS, 4000)
+    ref = oracle.lookup(t, q.E, q.mat)
+    ref32 = oracle.lookup_f32(t, q.E, q.mat)
+    return dict(t=t, q=q, h=h, E=dev(q.E, torch.float64),
+                m=dev(q.mat, torch.int32), ref=ref, ref32=ref32)
+
+
+@pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
+def test_cfg1_fp64_matches_oracle(cfg1, grid):
+    say("cfg1 fp64", grid)
+    out = run(cfg1["h"], cfg1["E"], cfg1["m"], grid=grid, sort="none",
+              block_size=256, lookups_per_thread=1)
+    assert rel_err(out, cfg1["ref"]).max() <= FP64_TOL
+    assert np.array_equal(out, cfg1["ref"])
+
+
+@pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
+def test_cfg1_fp32_matches_oracle(cfg1, grid):
+    say("cfg1 fp32", grid)
+    out = run(cfg1["h"], cfg1["E"], cfg1["m"], precision=xs.XS_FP32, grid=grid,
+              sort="material_energy", block_size=256, lookups_per_thread=2)
+    assert out.dtype == np.float32
+    err = rel_err(out, cfg1["ref"])
+    say("fp32 rel err max per channel", err.max(axis=0), "mean", err.mean(axis=0))
+    assert err.max() <= FP32_TOL
+    assert np.array_equal(out, cfg1["ref32"])
+
+
+@pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
+def test_cfg1_indices_bit_exact(cfg1, grid):
+    say("cfg1 indices", grid)
+    t, q = cfg1["t"], cfg1["q"]
+    _, idx_ref, off = oracle.lookup(t, q.E, q.mat, with_index=True)
+    idx = xs.xs_lookup_indices(cfg1["h"], cfg1["E"], cfg1["m"],
+                               dev(off, torch.int64), grid=grid)
+    torch.cuda.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), idx_ref)
+
+
+KNOBS = [
+    dict(sort="none", block_size=64, lookups_per_thread=1),
+    dict(sort="none", block_size=1024, lookups_per_thread=2),
+    dict(sort="material", sort_threshold=0, block_size=128, lookups_per_thread=3),
+    dict(sort="energy", sort_threshold=0, block_size=512, lookups_per_thread=4),
+    dict(sort="material_energy", sort_threshold=0, block_size=256,
+         lookups_per_thread=8),
+    dict(sort="material_energy", sort_threshold=xs.INT64_MAX, block_size=192,
+         lookups_per_thread=5),
+    dict(sort="material_energy", sort_threshold=20000, block_size=64,
+         lookups_per_thread=7),
+]
+
+
+@pytest.mark.parametrize("precision", [xs.XS_FP64, xs.XS_FP32])
+@pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
+def test_knobs_never_change_bits(cfg1, grid, precision):
+    say("knobs", grid, precision)
+    ref = cfg1["ref"] if precision == xs.XS_FP64 else cfg1["ref32"]
+    for k in KNOBS:
+        out = run(cfg1["h"], cfg1["E"], cfg1["m"], precision=precision,
+                  grid=grid, **k)
+        assert np.array_equal(out, ref), k
+
+
+def test_default_params(cfg1):
+    out = xs.xs_lookup_batch(cfg1["h"], cfg1["E"], cfg1["m"])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), cfg1["ref"])
+    p = xs.xs_resolve_params(cfg1["h"], 100000)
+    assert p.grid == xs.XS_GRID_HASH and p.block_size == 256
+
+
+def test_edge_queries(cfg1):
+    """Grid points of every nuclide, their neighbours, out-of-range energies,
+    invalid energies and materials."""
+    t = cfg1["t"]
+    pts = []
+    for k in range(t.n_nuclides):
+        g = t.grid(k)
+        pts += [g, np.nextafter(g, 0), np.nextafter(g, np.inf)]
+    E = np.concatenate(pts + [np.array([1e-9, 1e-6, 2.0, 1e30])])
+    m = np.arange(len(E), dtype=np.int32) % t.n_materials
+    E2 = np.concatenate([E, [np.nan, -1.0, 0.0, np.inf, 0.5, 0.5]])
+    m2 = np.concatenate([m, np.array([0, 1, 2, 3, 4, -1], np.int32)])
+    ref = oracle.lookup(t, E2, m2)
+    ref32 = oracle.lookup_f32(t, E2, m2)
+    for grid in ("nuclide", "hash", "unionized"):
+        for k in KNOBS[:3] + KNOBS[4:5]:
+            out = run(cfg1["h"], dev(E2, torch.float64), dev(m2, torch.int32),
+                      grid=grid, **k)
+            np.testing.assert_array_equal(out, ref)
+            out = run(cfg1["h"], dev(E2, torch.float64), dev(m2, torch.int32),
+                      precision=xs.XS_FP32, grid=grid, **k)
+            np.testing.assert_array_equal(out, ref32)
+    assert np.all(np.isnan(ref[-6:]))
+
+
+def test_empty_and_tiny(cfg1):
+    h = cfg1["h"]
+    E = cfg1["E"][:0]
+    m = cfg1["m"][:0]
+    out = xs.xs_lookup_batch(h, E, m)
+    assert out.shape == (0, 5)
+    for n in (1, 2, 63, 65, 257, 4097):
+        out = run(h, cfg1["E"][:n], cfg1["m"][:n], sort="material_energy",
+                  sort_threshold=0, lookups_per_thread=3, block_size=64)
+        assert np.array_equal(out, cfg1["ref"][:n]), n
+
+
+def test_degenerate_tables():
+    """Two-point nuclides, one-nuclide materials, one hash bin, one material."""
+    t = synth.random_tables(31, 6, [2, 2, 3, 50, 2, 700], 5,
+                            sizes=[1, 6, 2, 1, 3])
+    q = synth.random_queries(31, t, 50_001, lo=1e-6, hi=3.0)
+    ref = oracle.lookup(t, q.E, q.mat)
+    ref32 = oracle.lookup_f32(t, q.E, q.mat)
+    E, m = dev(q.E, torch.float64), dev(q.mat, torch.int32)
+    for bins in (1, 100, 4000, 100000):
+        h = xs.xs_create_tables(t, ALL_FLAGS, bins)
+        for grid in ("nuclide", "hash", "unionized"):
+            out = run(h, E, m, grid=grid, sort="material_energy", sort_threshold=0)
+            assert np.array_equal(out, ref), (bins, grid)
+            out = run(h, E, m, precision=xs.XS_FP32, grid=grid, sort="none")
+            assert np.array_equal(out, ref32), (bins, grid)
+        h.close()
+    one = synth.random_tables(32, 3, 40, 1, sizes=[3])
+    q1 = synth.random_queries(32, one, 1000)
+    h = xs.xs_create_tables(one, ALL_FLAGS, 64)
+    out = run(h, dev(q1.E, torch.float64), dev(q1.mat, torch.int32),
+              sort="material_energy", sort_threshold=0)
+    assert np.array_equal(out, oracle.lookup(one, q1.E, q1.mat))
+
+
+@pytest.mark.parametrize("bins", [1, 100, 4000, 8192, 100000])
+def test_hash_bins_indices(cfg1, bins):
+    t, q = cfg1["t"], cfg1["q"]
+    _, idx_ref, off = oracle.lookup(t, q.E[:20000], q.mat[:20000], with_index=True)
+    h = xs.xs_create_tables(t, xs.XS_BUILD_HASH, bins)
+    idx = xs.xs_lookup_indices(h, cfg1["E"][:20000], cfg1["m"][:20000],
+                               dev(off, torch.int64), grid="hash")
+    torch.cuda.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), idx_ref)
+    h.close()
+
+
+@pytest.mark.parametrize("queue", [xs.XS_QUEUE_COMPACT, xs.XS_QUEUE_PREDICATED])
+@pytest.mark.parametrize("sort", ["none", "material_energy"])
+def test_active_mask(cfg1, queue, sort):
+    """Inactive slots keep their sentinel; active ones match the oracle."""
+    n = len(cfg1["q"])
+    s = synth.Stream(33, 1)
+    act = (s.uniform(n) < 0.3).astype(np.uint8)
+    sentinel = -7.25
+    for prec, ref in ((xs.XS_FP64, cfg1["ref"]), (xs.XS_FP32, cfg1["ref32"])):
+        dt = torch.float64 if prec == xs.XS_FP64 else torch.float32
+        out = torch.full((n, 5), sentinel, dtype=dt, device="cuda:0")
+        p = xs.make_params(precision=prec, sort=sort, sort_threshold=0,
+                           queue=queue, lookups_per_thread=2)
+        xs.xs_lookup_active(cfg1["h"], cfg1["E"], cfg1["m"],
+                            dev(act, torch.uint8), out, params=p)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        a = act.astype(bool)
+        assert np.all(o[~a] == sentinel)
+        assert np.array_equal(o[a], ref[a])
+
+
+def test_errors_from_device_calls(cfg1):
+    h = cfg1["h"]
+    with pytest.raises(xs.XsError) as e:
+        xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
+                           params=xs.make_params(block_size=100))
+    assert e.value.status == xs.XS_EINVAL
+    with pytest.raises(xs.XsError) as e:
+        xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
+                           params=xs.make_params(block_size=1024,
+                                                 lookups_per_thread=5))
+    assert e.value.status == xs.XS_EINVAL
+    small = xs.xs_create_tables(cfg1["t"], 0, 0)
+    for p in (xs.make_params(grid="hash"), xs.make_params(grid="unionized"),
+              xs.make_params(precision=xs.XS_FP32, grid="nuclide")):
+        with pytest.raises(xs.XsError) as e:
+            xs.xs_lookup_batch(small, cfg1["E"], cfg1["m"], params=p)
+        assert e.value.status == xs.XS_ENOTBUILT
+    # too small a workspace
+    p = xs.make_params(sort="material_energy", sort_threshold=0)
+    need = xs.xs_workspace_size(h, 1000, p)
+    assert need > 0
+    ws = torch.empty(need // 2, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(xs.XsError) as e:
+        xs.xs_lookup_batch(h, cfg1["E"][:1000], cfg1["m"][:1000], params=p,
+                           workspace=(ws, ws.data_ptr(), need // 2))
+    assert e.value.status == xs.XS_EWORKSPACE
+    small.close()
+
+
+def test_table_info(cfg1):
+    info = xs.xs_table_info(cfg1["h"])
+    t = cfg1["t"]
+    assert info["n_nuclides"] == 20 and info["n_materials"] == 4
+    assert info["n_points"] == len(t.energy)
+    assert info["union_size"] == len(np.unique(t.energy))
+    assert info["n_hash_bins"] == 4000
+    assert info["e_min"] == 1e-5 and info["e_max"] == 1.0
+
+
+def test_profile_counts(cfg1):
+    h = cfg1["h"]
+    xs.xs_profile_begin(h)
+    for _ in range(3):
+        xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
+                           params=xs.make_params(sort="material_energy",
+                                                 sort_threshold=0))
+    prof = xs.xs_profile_end(h)
+    assert prof["calls"] == 3 and prof["sorted_calls"] == 3
+    assert prof["lookups"] == 3 * len(cfg1["q"])
+    assert prof["ms_lookup"] > 0 and prof["ms_sort"] > 0
+    assert prof["ms_total"] >= prof["ms_lookup"]
