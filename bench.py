@@ -140,6 +140,10 @@ def main(argv=None):
                     help="JSON dict of FP32 params instead of tuning")
     ap.add_argument("--only", choices=["plain", "tuned"], default=None,
                     help="time one form only (for profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain device copy of 2 GiB and exit (the "
+                         "achievable-bandwidth figure and the reference for "
+                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -150,6 +154,18 @@ def main(argv=None):
     import torch
     import synth
     from paper_2402_09222_amd import xs
+
+    if args.copy_probe:
+        nbytes = 2 << 30
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        sec = time_steps(lambda: dst.copy_(src), args.steps, args.warmup)
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "ms": sec * 1e3,
+                          "gbs_read_plus_write": 2 * nbytes / sec / 1e9}),
+              flush=True)
+        return 0
 
     log("generating config-2 tables and queries")
     t = synth.config2_tables()

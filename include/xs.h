@@ -68,11 +68,18 @@ typedef int32_t xs_status;
                       FP32 interpolation, Kahan-compensated FP32 sum, FP32
                       output */
 
-/* Reordering of lookups before the lookup kernel (never changes values). */
+/* Reordering of lookups before the lookup kernel (never changes values).
+ * Paper section 5.1 ("minimum sorting threshold"): sorting puts neighbouring
+ * particles in the same material and close in energy.  BAND_MATERIAL orders
+ * by a coarse energy band first, then material, then energy inside the band:
+ * lookups in flight together then cover a narrow energy range of every
+ * nuclide (a small cache footprint) while each wave still holds a single
+ * material. */
 #define XS_SORT_NONE 0
 #define XS_SORT_MATERIAL 1
 #define XS_SORT_ENERGY 2
 #define XS_SORT_MATERIAL_ENERGY 3
+#define XS_SORT_BAND_MATERIAL 4
 
 /* xs_lookup_active: how inactive slots are skipped. */
 #define XS_QUEUE_COMPACT 0     /* queued: compact active lookups, then look up */
@@ -116,21 +123,24 @@ typedef struct {
  * `precision` may be XS_AUTO (or 0 for block_size / lookups_per_thread), in
  * which case the value recorded by xs_tune for this precision and batch size
  * is used, else the library default (grid HASH if built else NUCLIDE, sort
- * MATERIAL_ENERGY at n >= 20,000, block 256, 1 lookup per thread).  The
+ * BAND_MATERIAL at n >= 20,000, block 256, 1 lookup per thread, 2 nuclides
+ * in flight).  The
  * choice never changes the results: every combination returns the same
  * indices and, within one precision, bit-identical sums. */
 typedef struct {
   int32_t precision;          /* XS_FP64 or XS_FP32 (output element type) */
   int32_t grid;               /* XS_GRID_* */
   int32_t sort;               /* XS_SORT_* */
-  int32_t block_size;         /* 64..1024, multiple of 64; at most 512 when
-                                 lookups_per_thread > 2 and 256 when > 4 */
+  int32_t block_size;         /* 64..1024, multiple of 64; with
+                                 w = lookups_per_thread * unroll, at most 512
+                                 when w > 2 and 256 when w > 4 */
   int32_t lookups_per_thread; /* 1..8 */
   int32_t lds_stage;          /* 0 or 1: stage grid segments in LDS */
   int64_t sort_threshold;     /* sort only when n >= sort_threshold
                                  (0 = always, INT64_MAX = never) */
   int32_t queue;              /* xs_lookup_active only: XS_QUEUE_* */
-  int32_t reserved;           /* must be 0 */
+  int32_t unroll;             /* nuclides in flight per lane: 1, 2 or 4
+                                 (2 and 4 need lookups_per_thread <= 2) */
 } xs_params;
 
 /* Sizes of a built handle. */
@@ -179,7 +189,8 @@ xs_status xs_table_info(xs_tables_t tables, xs_table_info_t* info);
 
 /* ---- parameters ---------------------------------------------------------- */
 
-/* Fills *p with XS_AUTO everywhere and the given precision. */
+/* Fills *p with XS_AUTO everywhere (0 for block_size, lookups_per_thread
+ * and unroll, -1 for sort_threshold) and the given precision. */
 xs_status xs_params_default(xs_params* p, int32_t precision);
 
 /* Resolves XS_AUTO fields for a batch of n lookups exactly as
@@ -226,6 +237,83 @@ xs_status xs_lookup_active(xs_tables_t tables, int64_t n, const double* d_E,
 xs_status xs_lookup_indices(xs_tables_t tables, int64_t n, const double* d_E,
                             const int32_t* d_mat, const int64_t* d_idx_offsets,
                             int32_t* d_idx, int32_t grid, void* stream);
+
+/* ---- tuning ---------------------------------------------------------------- */
+
+/* Search strategies.  FOREST is the paper's method (section 2.1): Bayesian
+ * optimisation with a random-forest surrogate of log(runtime) and the
+ * lower-confidence-bound acquisition a(x) = mu(x) - kappa sigma(x) (Eq. 1),
+ * sigma being the spread of the trees' predictions. */
+#define XS_TUNE_EXHAUSTIVE 0
+#define XS_TUNE_FOREST 1
+
+typedef struct {
+  int32_t precision;      /* XS_FP64 or XS_FP32 */
+  int32_t strategy;       /* XS_TUNE_* */
+  int32_t max_evals;      /* FOREST: evaluations including the baseline and
+                             the initial random ones (<= 0: whole space) */
+  int32_t init_samples;   /* FOREST: random configurations before the first
+                             surrogate fit */
+  int32_t batch;          /* FOREST: configurations proposed per fit (the
+                             paper's workers per batch); >= 1 */
+  int32_t reps;           /* timed runs per configuration, best kept (the
+                             paper reports the best of 5) */
+  int32_t warmup;         /* untimed runs per configuration */
+  int32_t reserved;       /* must be 0 */
+  double timeout_factor;  /* a configuration whose first timed run exceeds
+                             factor x the baseline's time is stopped and
+                             scored at that time-out (paper: 1.5); <= 0
+                             disables */
+  double kappa;           /* LCB weight, >= 0 (paper default 1.96) */
+  uint64_t seed;          /* random initial samples and bootstrap draws */
+  uint32_t grid_mask;     /* bit g: consider grid method g (0 = all built) */
+  uint32_t sort_mask;     /* bit s: consider sort policy s (0 = all) */
+} xs_tune_config;
+
+typedef struct {
+  xs_params best;         /* fully resolved, no XS_AUTO fields */
+  double best_ms;
+  xs_params baseline;     /* the library default, evaluated first */
+  double baseline_ms;
+  int32_t evaluated;      /* configurations run, baseline included */
+  int32_t cut;            /* of which stopped at the time-out */
+  int32_t space_size;     /* valid configurations in the space */
+  int32_t best_eval;      /* 1-based evaluation at which `best` was found */
+} xs_tune_result;
+
+/* Evaluator used by xs_tune_search: run configuration *p and store its time
+ * in *ms (milliseconds).  It may stop early once the time exceeds cutoff_ms
+ * (infinity until the baseline is known) and report any value above it.
+ * Returns XS_OK or an error status, which aborts the search. */
+typedef xs_status (*xs_eval_fn)(const xs_params* p, double cutoff_ms,
+                                double* ms, void* user);
+
+/* Fills *c with the defaults: FOREST, 48 evaluations, 10 initial samples,
+ * batch 1, best of 5 after 1 warm-up, time-out 1.5x baseline, kappa 1.96,
+ * seed 1234, all grids and sorts. */
+xs_status xs_tune_config_default(xs_tune_config* c);
+
+/* Searches the space of (grid method in built_grids & grid_mask) x (sort
+ * policy) x (block size 64..1024) x (lookups per lane, nuclides in flight),
+ * invalid combinations excluded, calling `eval` for each configuration it
+ * picks.  No device call of its own. */
+xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
+                         xs_eval_fn eval, void* user, xs_tune_result* result);
+
+/* Tunes xs_lookup_batch for batches of n lookups on the caller's sample
+ * (DEVICE d_E / d_mat [n], d_out [n][5] of the precision's type, d_ws at
+ * least xs_workspace_size(n) with a sort), timing each configuration with
+ * HIP events on `stream`, and records the winner in the handle for the
+ * batch-size class floor(log2 n): later calls whose fields are XS_AUTO use
+ * the tuned value of the nearest class.  Synchronises `stream`. */
+xs_status xs_tune(xs_tables_t tables, int64_t n, const double* d_E,
+                  const int32_t* d_mat, void* d_out, void* d_ws,
+                  size_t ws_bytes, void* stream, const xs_tune_config* cfg,
+                  xs_tune_result* result);
+
+/* Records complete parameters (no XS_AUTO field) as tuned for the class of
+ * n, e.g. restored from a cache file; p == NULL clears every tuned entry. */
+xs_status xs_set_tuned(xs_tables_t tables, int64_t n, const xs_params* p);
 
 /* ---- measurement --------------------------------------------------------- */
 

@@ -174,7 +174,6 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
     return fail(XS_EINVAL, "precision must be XS_FP64 or XS_FP32");
   if (p.precision == XS_FP32 && !h->d.rec32)
     return fail(XS_ENOTBUILT, "FP32 tables were not built (XS_BUILD_FP32)");
-  if (p.reserved != 0) return fail(XS_EINVAL, "reserved field must be 0");
 
   xs_params t;
   bool have_tuned = false;
@@ -189,13 +188,13 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (!have_tuned) {
     t.precision = p.precision;
     t.grid = h->d.B > 0 ? XS_GRID_HASH : XS_GRID_NUCLIDE;
-    t.sort = XS_SORT_MATERIAL_ENERGY;
+    t.sort = XS_SORT_BAND_MATERIAL;
     t.block_size = 256;
     t.lookups_per_thread = 1;
     t.lds_stage = 0;
     t.sort_threshold = 20000;
     t.queue = XS_QUEUE_COMPACT;
-    t.reserved = 0;
+    t.unroll = 2;
   }
   if (p.grid == XS_AUTO) p.grid = t.grid;
   if (p.sort == XS_AUTO) p.sort = t.sort;
@@ -205,41 +204,61 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.lds_stage == XS_AUTO) p.lds_stage = t.lds_stage;
   if (p.sort_threshold < 0) p.sort_threshold = t.sort_threshold;
   if (p.queue == XS_AUTO) p.queue = t.queue;
+  if (p.unroll == 0 || p.unroll == XS_AUTO)
+    p.unroll = p.lookups_per_thread <= 2 ? t.unroll : 1;
 
   if (p.grid < 0 || p.grid > 2) return fail(XS_EINVAL, "unknown grid %d", p.grid);
   if (p.grid == XS_GRID_HASH && h->d.B == 0)
     return fail(XS_ENOTBUILT, "hash grid was not built (XS_BUILD_HASH)");
   if (p.grid == XS_GRID_UNIONIZED && h->d.U == 0)
     return fail(XS_ENOTBUILT, "unionized grid was not built (XS_BUILD_UNIONIZED)");
-  if (p.sort < 0 || p.sort > 3) return fail(XS_EINVAL, "unknown sort %d", p.sort);
+  if (p.sort < 0 || p.sort > 4) return fail(XS_EINVAL, "unknown sort %d", p.sort);
   if (p.block_size < 64 || p.block_size > 1024 || p.block_size % 64)
     return fail(XS_EINVAL, "block_size %d not in 64..1024 step 64", p.block_size);
   if (p.lookups_per_thread < 1 || p.lookups_per_thread > 8)
     return fail(XS_EINVAL, "lookups_per_thread %d not in 1..8",
                 p.lookups_per_thread);
-  {
-    const int lpt = p.lookups_per_thread;
-    const int max_block = lpt <= 2 ? 1024 : (lpt <= 4 ? 512 : 256);
-    if (p.block_size > max_block)
-      return fail(XS_EINVAL, "block_size %d too large for %d lookups per thread "
-                  "(max %d)", p.block_size, lpt, max_block);
-  }
   if (p.lds_stage != 0 && p.lds_stage != 1)
     return fail(XS_EINVAL, "lds_stage must be 0 or 1");
   if (p.lds_stage == 1)
     return fail(XS_EINVAL, "lds_stage = 1 is not available in this build");
   if (p.queue != XS_QUEUE_COMPACT && p.queue != XS_QUEUE_PREDICATED)
     return fail(XS_EINVAL, "unknown queue mode %d", p.queue);
+  if (p.unroll != 1 && p.unroll != 2 && p.unroll != 4)
+    return fail(XS_EINVAL, "unroll %d not 1, 2 or 4", p.unroll);
+  if (p.unroll > 1 && p.lookups_per_thread > 2)
+    return fail(XS_EINVAL, "unroll %d needs lookups_per_thread <= 2",
+                p.unroll);
+  {
+    const int w = p.lookups_per_thread * p.unroll;
+    const int max_block = w <= 2 ? 1024 : (w <= 4 ? 512 : 256);
+    if (p.block_size > max_block)
+      return fail(XS_EINVAL, "block_size %d too large for %d lookups per lane "
+                  "x %d nuclides in flight (max %d)", p.block_size,
+                  p.lookups_per_thread, p.unroll, max_block);
+  }
   *out = p;
   return XS_OK;
 }
 
-SortKey make_sort_key(const xs_tables_s* h, int sort, bool flag) {
+SortKey make_sort_key(const xs_tables_s* h, int sort, bool flag, int64_t n) {
   SortKey k{};
   k.M = h->d.M;
   k.flag_bit = flag ? 1 : 0;
   const int mb = ceil_log2(h->d.M);
   switch (sort) {
+    case XS_SORT_BAND_MATERIAL: {
+      // About 1024 lookups per (band, material) group: whole waves stay in
+      // one material, and the bands are fine enough that the lookups in
+      // flight on an XCD span a narrow energy range.
+      int bb = 0;
+      while (bb < 12 && (n >> (bb + 1)) >= (int64_t)h->d.M * 1024) ++bb;
+      k.band_bits = bb;
+      k.mat_bits = mb;
+      k.e_bits = 24 - mb - k.flag_bit;
+      if (k.e_bits < bb + 1) k.e_bits = 32 - mb - k.flag_bit;
+      break;
+    }
     case XS_SORT_MATERIAL:
       k.mat_bits = std::max(mb, 1);
       k.e_bits = 0;
@@ -298,7 +317,7 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
 
   const bool do_sort = p.sort != XS_SORT_NONE && n >= p.sort_threshold;
   const bool compact = masked && !do_sort && p.queue == XS_QUEUE_COMPACT;
-  const SortKey key = do_sort ? make_sort_key(h, p.sort, masked) : SortKey{};
+  const SortKey key = do_sort ? make_sort_key(h, p.sort, masked, n) : SortKey{};
   const size_t need = do_sort   ? sort_workspace_bytes(n, key.total_bits)
                       : compact ? compact_workspace_bytes(n)
                                 : 0;
@@ -521,7 +540,7 @@ xs_status xs_params_default(xs_params* p, int32_t precision) {
   p->lds_stage = XS_AUTO;
   p->sort_threshold = -1;
   p->queue = XS_AUTO;
-  p->reserved = 0;
+  p->unroll = 0;
   return XS_OK;
 }
 

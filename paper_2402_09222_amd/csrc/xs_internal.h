@@ -62,9 +62,12 @@ struct DevTables {
 };
 
 // ---- sort key ------------------------------------------------------------
+// Layout, high to low: [inactive flag][energy band][material][energy rest].
+// Without a band (band_bits = 0) the material sits above all energy bits.
 struct SortKey {
   int32_t mat_bits;   // bits of the material field (0 = not in the key)
-  int32_t e_bits;     // bits of the energy field (0 = not in the key)
+  int32_t e_bits;     // bits of the energy key (0 = not in the key)
+  int32_t band_bits;  // top bits of the energy key placed above the material
   int32_t e_shift;    // right shift applied to (bits(E) - bits(e_min))
   int32_t flag_bit;   // 1: an "inactive" flag sits above the other fields
   int64_t e_bits_min; // IEEE bit pattern of e_min

@@ -1,6 +1,6 @@
-// Lookup kernels, templated on grid method, precision and lookups per lane.
-// Included by one translation unit per grid method so they compile in
-// parallel.
+// Lookup kernels, templated on grid method, precision, lookups per lane
+// (LPT) and nuclides in flight per lane (U).  Included by one translation
+// unit per grid method so they compile in parallel.
 //
 // Per lookup (paper section 5.1, hash-bin paragraph after Table 1): for each
 // nuclide of the material, in list order, find the bracket of E in the
@@ -9,6 +9,13 @@
 // fixed (same operations, same order, no fused multiply-add: the library is
 // built with -ffp-contract=off), so every grid method, sort order and launch
 // shape gives bit-identical sums within one precision.
+//
+// The walk over a material's nuclides is latency-bound (dependent loads:
+// index, then the bracketing records), so each lane keeps U nuclides in
+// flight: it issues the index loads of U nuclides, then their record loads,
+// then adds the U terms in list order.  When every lane of a wave holds the
+// same material (the usual case after a sort) the material list is read with
+// scalar loads.
 #pragma once
 
 #include "xs_internal.h"
@@ -32,6 +39,22 @@ __device__ __forceinline__ bool valid_query(double e, int m, int M) {
   return __builtin_isfinite(e) && e > 0.0 && (unsigned)m < (unsigned)M;
 }
 
+// Reads through the constant address space: with a wave-uniform address the
+// compiler emits a scalar load; with a per-lane address a vector load.  Only
+// used for tables that no kernel writes.
+template <class T>
+__device__ __forceinline__ T ld_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized types only");
+  typedef const __attribute__((address_space(4))) uint32_t* WordPtr;
+  const WordPtr q = (WordPtr)p;
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = q[i];
+  T v;
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+
 // Block index remapped so that each XCD (blocks are dealt round-robin to
 // the 8 XCDs) runs one contiguous eighth of the blocks: neighbouring blocks,
 // which after a sort touch neighbouring grid segments, then share an L2.
@@ -40,68 +63,146 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   return x * q + (x < r ? x : r) + s;
 }
 
-// ---- bracket search per grid method --------------------------------------
+// Largest block for LPT lookups per lane with U nuclides in flight: more
+// independent chains per lane need more registers, so fewer lanes fit per
+// compute unit.
+constexpr int max_block_for(int lpt, int unroll) {
+  return lpt * unroll <= 2 ? 1024 : (lpt * unroll <= 4 ? 512 : 256);
+}
+
+// ---- records per precision ---------------------------------------------------
+
+template <int PREC>
+struct RecOf;
+template <>
+struct RecOf<XS_FP64> {
+  using T = Rec64;
+  __device__ static const Rec64* base(const DevTables& t) { return t.rec64; }
+};
+template <>
+struct RecOf<XS_FP32> {
+  using T = Rec32;
+  __device__ static const Rec32* base(const DevTables& t) { return t.rec32; }
+};
+
+// Bracket test against the pair's energies (with the clamp cases).
+template <class R>
+__device__ __forceinline__ bool bracket_ok(int i, int n, double e, const R& lo,
+                                           const R& hi) {
+  return (i == 0 || lo.e <= e) && (i == n - 2 || e < hi.e);
+}
+
+// ---- hash-bin search ------------------------------------------------------------
+//
+// H[b][k] is nuclide k's bracket at the lower edge of bin b, so for E in bin b
+// the bracket lies in [H[b][k], H[b+1][k]].  The fast path assumes it is
+// H[b][k] or H[b][k] + 1 (true whenever a bin holds at most one grid point of
+// the nuclide): it reads the three records from H[b][k] on and keeps the pair
+// that brackets E.  Otherwise the slow path scans the bin's window and, if
+// rounding of log() put E in a neighbouring bin, bisects the whole grid.
+// Either way the result is the unique bracket.
+
+__device__ __forceinline__ int hash_slow(const DevTables& t, const MatRec& r,
+                                         const int32_t* hrow1, int lo,
+                                         double e) {
+  const double* g = t.E + r.base;
+  const int hi = hrow1[r.k];
+  int p = lo;
+  while (p < hi && g[p + 1] <= e) ++p;
+  const bool ok = (p == 0 || g[p] <= e) && (p == r.n - 2 || e < g[p + 1]);
+  return ok ? p : min(bisect_le(g, r.n, e), r.n - 2);
+}
+
+// ---- per-lookup search state ---------------------------------------------------
 
 template <int GRID>
 struct Locator;
 
-// Bisection of the nuclide's own grid.
 template <>
 struct Locator<XS_GRID_NUCLIDE> {
-  static constexpr bool kVerify = false;
   __device__ __forceinline__ void init(const DevTables&, double) {}
-  __device__ __forceinline__ int bracket(const DevTables& t, const MatRec& r,
-                                         double e) const {
+  __device__ __forceinline__ int start(const DevTables& t, const MatRec& r,
+                                       double e) const {
     return min(bisect_le(t.E + r.base, r.n, e), r.n - 2);
+  }
+  __device__ __forceinline__ const int32_t* next_row(const DevTables&) const {
+    return nullptr;
   }
 };
 
-// Logarithmic hash bins: bin b of E is computed once per lookup; H[b][k] and
-// H[b+1][k] bound nuclide k's bracket, found by a short forward scan.  A
-// verification against the bracketing energies (done by the caller) falls
-// back to bisection when rounding of log() put E in a neighbouring bin.
 template <>
 struct Locator<XS_GRID_HASH> {
-  static constexpr bool kVerify = true;
-  int b;
+  const int32_t* hrow;  // H[b]
   __device__ __forceinline__ void init(const DevTables& t, double e) {
     double x = (log(e) - t.ln_emin) * t.inv_dln;
     x = fmin(fmax(x, 0.0), (double)(t.B - 1));
-    b = (int)x;
+    hrow = t.H + (int64_t)(int)x * t.K;
   }
-  __device__ __forceinline__ int bracket(const DevTables& t, const MatRec& r,
-                                         double e) const {
-    const int32_t* h = t.H + (int64_t)b * t.K + r.k;
-    const int lo = h[0], hi = h[t.K];
-    const double* g = t.E + r.base;
-    int p = lo;
-    while (p < hi && g[p + 1] <= e) ++p;
-    return p;
+  __device__ __forceinline__ int start(const DevTables&, const MatRec& r,
+                                       double) const {
+    return hrow[r.k];
+  }
+  __device__ __forceinline__ const int32_t* next_row(const DevTables& t) const {
+    return hrow + t.K;  // H[b+1]
   }
 };
 
-// Unionized grid: one bisection of the union of all grids per lookup, then
-// one index-table read per nuclide.
 template <>
 struct Locator<XS_GRID_UNIONIZED> {
-  static constexpr bool kVerify = false;
-  int j;
+  const int32_t* urow;  // uidx[j]
   __device__ __forceinline__ void init(const DevTables& t, double e) {
-    j = bisect_le(t.u, (int)t.U, e);
+    urow = t.uidx + (int64_t)bisect_le(t.u, (int)t.U, e) * t.K;
   }
-  __device__ __forceinline__ int bracket(const DevTables& t, const MatRec& r,
-                                         double) const {
-    return t.uidx[(int64_t)j * t.K + r.k];
+  __device__ __forceinline__ int start(const DevTables&, const MatRec& r,
+                                       double) const {
+    return urow[r.k];
+  }
+  __device__ __forceinline__ const int32_t* next_row(const DevTables&) const {
+    return nullptr;
   }
 };
 
-// ---- one (lookup, nuclide) step --------------------------------------------
-
-template <class R>
-__device__ __forceinline__ bool bracket_ok(int i, int n, double e,
-                                           const R& lo, const R& hi) {
-  return (i == 0 || lo.e <= e) && (i == n - 2 || e < hi.e);
-}
+// Records around a candidate index: three for the hash grid (candidate and
+// the next two), two (the bracket) otherwise.
+template <int GRID, int PREC>
+struct Window {
+  using R = typename RecOf<PREC>::T;
+  static constexpr int kN = GRID == XS_GRID_HASH ? 3 : 2;
+  R r[kN];
+  __device__ __forceinline__ void load(const DevTables& t, const MatRec& m,
+                                       int i) {
+    const R* p = RecOf<PREC>::base(t) + m.base;
+    r[0] = p[i];
+    r[1] = p[i + 1];
+    if (kN == 3) r[kN - 1] = p[min(i + 2, m.n - 1)];
+  }
+  // Final bracket pair into lo/hi.
+  __device__ __forceinline__ void finish(const DevTables& t, const MatRec& m,
+                                         const Locator<GRID>& loc, int cand,
+                                         double e, R& lo, R& hi) const {
+    if (GRID != XS_GRID_HASH) {
+      lo = r[0];
+      hi = r[1];
+      return;
+    }
+    int i;
+    if (cand + 1 <= m.n - 2 && r[1].e <= e) {
+      i = cand + 1;
+      lo = r[1];
+      hi = r[kN - 1];
+    } else {
+      i = cand;
+      lo = r[0];
+      hi = r[1];
+    }
+    if (!bracket_ok(i, m.n, e, lo, hi)) {
+      i = hash_slow(t, m, loc.next_row(t), cand, e);
+      const R* p = RecOf<PREC>::base(t) + m.base;
+      lo = p[i];
+      hi = p[i + 1];
+    }
+  }
+};
 
 // Clamped energy and fraction.  min(max(E, E_k[0]), E_k[n-1]) equals
 // min(max(E, E_k[i]), E_k[i+1]) for the bracket i, so only the bracket's
@@ -110,69 +211,6 @@ __device__ __forceinline__ double fraction(double e, double e0, double e1) {
   double eh = e < e0 ? e0 : e;
   eh = eh > e1 ? e1 : eh;
   return (eh - e0) / (e1 - e0);
-}
-
-template <int GRID>
-__device__ __forceinline__ void step64(const DevTables& t,
-                                       const Locator<GRID>& loc, int j,
-                                       double e, double acc[XS_CHANNELS]) {
-  const MatRec r = t.mrec[j];
-  int i = loc.bracket(t, r, e);
-  const Rec64* rp = t.rec64 + r.base + i;
-  Rec64 lo = rp[0], hi = rp[1];
-  if (Locator<GRID>::kVerify && !bracket_ok(i, r.n, e, lo, hi)) {
-    i = min(bisect_le(t.E + r.base, r.n, e), r.n - 2);
-    rp = t.rec64 + r.base + i;
-    lo = rp[0];
-    hi = rp[1];
-  }
-  const double f = fraction(e, lo.e, hi.e);
-  const double g = 1.0 - f;
-  const double rho = t.rho64[j];
-#pragma unroll
-  for (int c = 0; c < XS_CHANNELS; ++c) {
-    const double a = g * lo.x[c];
-    const double b = f * hi.x[c];
-    const double sigma = a + b;
-    const double term = rho * sigma;
-    acc[c] = acc[c] + term;
-  }
-}
-
-struct Kahan32 {
-  float s[XS_CHANNELS];
-  float c[XS_CHANNELS];
-};
-
-template <int GRID>
-__device__ __forceinline__ void step32(const DevTables& t,
-                                       const Locator<GRID>& loc, int j,
-                                       double e, Kahan32& acc) {
-  const MatRec r = t.mrec[j];
-  int i = loc.bracket(t, r, e);
-  const Rec32* rp = t.rec32 + r.base + i;
-  Rec32 lo = rp[0], hi = rp[1];
-  if (Locator<GRID>::kVerify && !bracket_ok(i, r.n, e, lo, hi)) {
-    i = min(bisect_le(t.E + r.base, r.n, e), r.n - 2);
-    rp = t.rec32 + r.base + i;
-    lo = rp[0];
-    hi = rp[1];
-  }
-  const double f = fraction(e, lo.e, hi.e);
-  const float f32 = (float)f;
-  const float g32 = (float)(1.0 - f);
-  const float rho = r.rho32;
-#pragma unroll
-  for (int c = 0; c < XS_CHANNELS; ++c) {
-    const float a = g32 * lo.x[c];
-    const float b = f32 * hi.x[c];
-    const float sigma = a + b;
-    const float term = rho * sigma;
-    const float y = term - acc.c[c];
-    const float tt = acc.s[c] + y;
-    acc.c[c] = (tt - acc.s[c]) - y;
-    acc.s[c] = tt;
-  }
 }
 
 // ---- accumulators and output per precision --------------------------------
@@ -187,11 +225,24 @@ struct Acc<XS_FP64> {
 #pragma unroll
     for (int c = 0; c < XS_CHANNELS; ++c) v[c] = 0.0;
   }
-  template <int GRID>
-  __device__ __forceinline__ void step(const DevTables& t,
-                                       const Locator<GRID>& loc, int j,
-                                       double e) {
-    step64<GRID>(t, loc, j, e, v);
+  // One nuclide's term: sigma = g*lo + f*hi (two products, one add), then
+  // sum += rho * sigma.
+  __device__ __forceinline__ void add(const Rec64& lo, const Rec64& hi,
+                                      double e, double rho) {
+    const double f = fraction(e, lo.e, hi.e);
+    const double g = 1.0 - f;
+#pragma unroll
+    for (int c = 0; c < XS_CHANNELS; ++c) {
+      const double a = g * lo.x[c];
+      const double b = f * hi.x[c];
+      const double sigma = a + b;
+      const double term = rho * sigma;
+      v[c] = v[c] + term;
+    }
+  }
+  __device__ __forceinline__ static double rho(const DevTables& t,
+                                               const MatRec&, int j) {
+    return ld_const(t.rho64 + j);
   }
   __device__ __forceinline__ void store(void* out, int64_t o) const {
     double* p = (double*)out + o * XS_CHANNELS;
@@ -207,47 +258,161 @@ struct Acc<XS_FP64> {
 
 template <>
 struct Acc<XS_FP32> {
-  Kahan32 k;
+  float s[XS_CHANNELS];
+  float c[XS_CHANNELS];
   __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int c = 0; c < XS_CHANNELS; ++c) {
-      k.s[c] = 0.0f;
-      k.c[c] = 0.0f;
+    for (int k = 0; k < XS_CHANNELS; ++k) {
+      s[k] = 0.0f;
+      c[k] = 0.0f;
     }
   }
-  template <int GRID>
-  __device__ __forceinline__ void step(const DevTables& t,
-                                       const Locator<GRID>& loc, int j,
-                                       double e) {
-    step32<GRID>(t, loc, j, e, k);
+  // f and g = 1 - f are formed in FP64 and each rounded to FP32; channels
+  // interpolate in FP32; the sum over nuclides is compensated (Kahan):
+  // y = rho*sigma - c; t = s + y; c = (t - s) - y; s = t.
+  __device__ __forceinline__ void add(const Rec32& lo, const Rec32& hi,
+                                      double e, float rho) {
+    const double f = fraction(e, lo.e, hi.e);
+    const float f32 = (float)f;
+    const float g32 = (float)(1.0 - f);
+#pragma unroll
+    for (int k = 0; k < XS_CHANNELS; ++k) {
+      const float a = g32 * lo.x[k];
+      const float b = f32 * hi.x[k];
+      const float sigma = a + b;
+      const float term = rho * sigma;
+      const float y = term - c[k];
+      const float tt = s[k] + y;
+      c[k] = (tt - s[k]) - y;
+      s[k] = tt;
+    }
+  }
+  __device__ __forceinline__ static float rho(const DevTables&, const MatRec& r,
+                                              int) {
+    return r.rho32;
   }
   __device__ __forceinline__ void store(void* out, int64_t o) const {
     float* p = (float*)out + o * XS_CHANNELS;
 #pragma unroll
-    for (int c = 0; c < XS_CHANNELS; ++c) p[c] = k.s[c];
+    for (int k = 0; k < XS_CHANNELS; ++k) p[k] = s[k];
   }
   __device__ __forceinline__ static void store_nan(void* out, int64_t o) {
     float* p = (float*)out + o * XS_CHANNELS;
 #pragma unroll
-    for (int c = 0; c < XS_CHANNELS; ++c) p[c] = __builtin_nanf("");
+    for (int k = 0; k < XS_CHANNELS; ++k) p[k] = __builtin_nanf("");
   }
 };
+
+// ---- walk of one material's nuclide list for LPT lookups ---------------------------
+//
+// `mat` is either wave-uniform (scalar loads of the list) or per lane.  U
+// nuclides are processed per iteration in three phases (index loads, record
+// loads, in-order accumulation), so a lane has U x LPT independent load
+// chains in flight.
+
+// Candidate indices of U nuclides for LPT lookups.  Bisection runs the
+// LPT x U searches in lock step so their probes overlap; the other methods
+// issue one index load each.
+template <int GRID, int LPT, int U>
+__device__ __forceinline__ void candidates(const DevTables& t,
+                                           const MatRec (&r)[U],
+                                           const double (&e)[LPT],
+                                           const Locator<GRID> (&loc)[LPT],
+                                           int (&cand)[LPT][U]) {
+  if (GRID == XS_GRID_NUCLIDE) {
+    int lo[LPT][U], len[LPT][U];
+#pragma unroll
+    for (int l = 0; l < LPT; ++l)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        lo[l][u] = 0;
+        len[l][u] = r[u].n;
+      }
+    bool more = true;
+    while (more) {
+      more = false;
+#pragma unroll
+      for (int l = 0; l < LPT; ++l)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (len[l][u] > 1) {
+            const int half = len[l][u] >> 1;
+            const double* g = t.E + r[u].base;
+            lo[l][u] = (g[lo[l][u] + half] <= e[l]) ? lo[l][u] + half : lo[l][u];
+            len[l][u] -= half;
+            more = more || len[l][u] > 1;
+          }
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < LPT; ++l)
+#pragma unroll
+      for (int u = 0; u < U; ++u) cand[l][u] = min(lo[l][u], r[u].n - 2);
+    return;
+  }
+#pragma unroll
+  for (int l = 0; l < LPT; ++l)
+#pragma unroll
+    for (int u = 0; u < U; ++u) cand[l][u] = loc[l].start(t, r[u], e[l]);
+}
+
+template <int GRID, int PREC, int LPT, int U>
+__device__ __forceinline__ void walk_material(const DevTables& t, int mat,
+                                              const double (&e)[LPT],
+                                              const Locator<GRID> (&loc)[LPT],
+                                              Acc<PREC> (&acc)[LPT]) {
+  using W = Window<GRID, PREC>;
+  using R = typename W::R;
+  const int j0 = ld_const(t.moff + mat), j1 = ld_const(t.moff + mat + 1);
+  int j = j0;
+  if (U > 1) {
+    for (; j + U <= j1; j += U) {
+      MatRec r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) r[u] = ld_const(t.mrec + j + u);
+      int cand[LPT][U];
+      candidates<GRID, LPT, U>(t, r, e, loc, cand);
+      W w[LPT][U];
+#pragma unroll
+      for (int l = 0; l < LPT; ++l)
+#pragma unroll
+        for (int u = 0; u < U; ++u) w[l][u].load(t, r[u], cand[l][u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const auto rho = Acc<PREC>::rho(t, r[u], j + u);
+#pragma unroll
+        for (int l = 0; l < LPT; ++l) {
+          R lo, hi;
+          w[l][u].finish(t, r[u], loc[l], cand[l][u], e[l], lo, hi);
+          acc[l].add(lo, hi, e[l], rho);
+        }
+      }
+    }
+  }
+  for (; j < j1; ++j) {
+    const MatRec r[1] = {ld_const(t.mrec + j)};
+    int cand[LPT][1];
+    candidates<GRID, LPT, 1>(t, r, e, loc, cand);
+    W w[LPT];
+#pragma unroll
+    for (int l = 0; l < LPT; ++l) w[l].load(t, r[0], cand[l][0]);
+    const auto rho = Acc<PREC>::rho(t, r[0], j);
+#pragma unroll
+    for (int l = 0; l < LPT; ++l) {
+      R lo, hi;
+      w[l].finish(t, r[0], loc[l], cand[l][0], e[l], lo, hi);
+      acc[l].add(lo, hi, e[l], rho);
+    }
+  }
+}
 
 // ---- the lookup kernel -------------------------------------------------------
 //
 // A block covers blockDim * LPT consecutive queue positions; lane l of the
-// block takes positions base + l, base + l + blockDim, ... (coalesced).  When
-// all of a lane's lookups share one material they walk its nuclide list
-// together, giving LPT independent searches per step.
+// block takes positions base + l, base + l + blockDim, ... (coalesced).
 
-// Largest block for LPT lookups per lane: more lookups per lane need more
-// registers, so fewer lanes fit per compute unit.
-constexpr int max_block_for_lpt(int lpt) {
-  return lpt <= 2 ? 1024 : (lpt <= 4 ? 512 : 256);
-}
-
-template <int GRID, int PREC, int LPT>
-__global__ __launch_bounds__(max_block_for_lpt(LPT)) void k_lookup(
+template <int GRID, int PREC, int LPT, int U>
+__global__ __launch_bounds__(max_block_for(LPT, U)) void k_lookup(
     const DevTables t, const LookupArgs a) {
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t n = a.count_dev ? *a.count_dev : a.n;
@@ -262,7 +427,7 @@ __global__ __launch_bounds__(max_block_for_lpt(LPT)) void k_lookup(
     const int64_t q = first + (int64_t)l * blockDim.x;
     act[l] = q < n;
     o[l] = 0;
-    e[l] = 0.0;
+    e[l] = 1.0;
     m[l] = -1;
     if (act[l]) {
       o[l] = a.perm ? (int64_t)a.perm[q] : q;
@@ -280,11 +445,15 @@ __global__ __launch_bounds__(max_block_for_lpt(LPT)) void k_lookup(
     }
   }
 
-  bool fuse = LPT > 1;
+  // All of this lane's lookups active and in one material?
+  bool same = true;
 #pragma unroll
-  for (int l = 0; l < LPT; ++l) fuse = fuse && act[l] && m[l] == m[0];
+  for (int l = 0; l < LPT; ++l) same = same && act[l] && m[l] == m[0];
+  // ... and the whole wave in that material?
+  const int mu = __builtin_amdgcn_readfirstlane(m[0]);
+  const bool wave_uniform = __all(same && m[0] == mu);
 
-  if (fuse) {
+  if (wave_uniform || same) {
     Locator<GRID> loc[LPT];
     Acc<PREC> acc[LPT];
 #pragma unroll
@@ -292,11 +461,10 @@ __global__ __launch_bounds__(max_block_for_lpt(LPT)) void k_lookup(
       loc[l].init(t, e[l]);
       acc[l].zero();
     }
-    const int j0 = t.moff[m[0]], j1 = t.moff[m[0] + 1];
-    for (int j = j0; j < j1; ++j) {
-#pragma unroll
-      for (int l = 0; l < LPT; ++l) acc[l].template step<GRID>(t, loc[l], j, e[l]);
-    }
+    if (wave_uniform)
+      walk_material<GRID, PREC, LPT, U>(t, mu, e, loc, acc);
+    else
+      walk_material<GRID, PREC, LPT, U>(t, m[0], e, loc, acc);
 #pragma unroll
     for (int l = 0; l < LPT; ++l) acc[l].store(a.out, o[l]);
     return;
@@ -305,17 +473,24 @@ __global__ __launch_bounds__(max_block_for_lpt(LPT)) void k_lookup(
 #pragma unroll
   for (int l = 0; l < LPT; ++l) {
     if (!act[l]) continue;
-    Locator<GRID> loc;
-    loc.init(t, e[l]);
-    Acc<PREC> acc;
-    acc.zero();
-    const int j0 = t.moff[m[l]], j1 = t.moff[m[l] + 1];
-    for (int j = j0; j < j1; ++j) acc.template step<GRID>(t, loc, j, e[l]);
-    acc.store(a.out, o[l]);
+    const double e1[1] = {e[l]};
+    Locator<GRID> loc[1];
+    Acc<PREC> acc[1];
+    loc[0].init(t, e[l]);
+    acc[0].zero();
+    walk_material<GRID, PREC, 1, U>(t, m[l], e1, loc, acc);
+    acc[0].store(a.out, o[l]);
   }
 }
 
 // ---- validation path: brackets of every (lookup, nuclide) ---------------------
+//
+// Uses the same candidate and window logic as the lookup, reading energies
+// from the search grid instead of the records.
+
+struct GridRec {
+  double e;
+};
 
 template <int GRID>
 __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
@@ -338,11 +513,22 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
   loc.init(t, e);
   for (int j = j0; j < j1; ++j) {
     const MatRec r = t.mrec[j];
-    int i = loc.bracket(t, r, e);
-    if (Locator<GRID>::kVerify) {
+    const int cand = loc.start(t, r, e);
+    int i = cand;
+    if (GRID == XS_GRID_HASH) {
       const double* g = t.E + r.base;
-      const bool ok = (i == 0 || g[i] <= e) && (i == r.n - 2 || e < g[i + 1]);
-      if (!ok) i = min(bisect_le(g, r.n, e), r.n - 2);
+      const GridRec g0{g[cand]}, g1{g[cand + 1]}, g2{g[min(cand + 2, r.n - 1)]};
+      GridRec lo, hi;
+      if (cand + 1 <= r.n - 2 && g1.e <= e) {
+        i = cand + 1;
+        lo = g1;
+        hi = g2;
+      } else {
+        lo = g0;
+        hi = g1;
+      }
+      if (!bracket_ok(i, r.n, e, lo, hi))
+        i = hash_slow(t, r, loc.next_row(t), cand, e);
     }
     out[j - j0] = i;
   }
@@ -350,33 +536,42 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 
 // ---- launchers ------------------------------------------------------------------
 
+// (LPT, U) pairs instantiated: every LPT with one nuclide in flight, and 2 or
+// 4 nuclides in flight for one or two lookups per lane.
+constexpr bool variant_exists(int lpt, int unroll) {
+  return (unroll == 1 && lpt >= 1 && lpt <= 8) ||
+         ((unroll == 2 || unroll == 4) && (lpt == 1 || lpt == 2));
+}
+
 template <int GRID, int PREC>
-hipError_t launch_lpt(const DevTables& t, int lpt, dim3 grid, dim3 block,
-                      const LookupArgs& a, hipStream_t s) {
-  switch (lpt) {
-#define XS_LPT_CASE(L)                                                      \
-  case L:                                                                   \
-    hipLaunchKernelGGL((k_lookup<GRID, PREC, L>), grid, block, 0, s, t, a); \
-    break;
-    XS_LPT_CASE(1)
-    XS_LPT_CASE(2)
-    XS_LPT_CASE(3)
-    XS_LPT_CASE(4)
-    XS_LPT_CASE(5)
-    XS_LPT_CASE(6)
-    XS_LPT_CASE(7)
-    XS_LPT_CASE(8)
-#undef XS_LPT_CASE
-    default:
-      return hipErrorInvalidValue;
+hipError_t launch_variant(const DevTables& t, int lpt, int unroll, dim3 grid,
+                          dim3 block, const LookupArgs& a, hipStream_t s) {
+#define XS_CASE(L, U)                                                          \
+  if (lpt == L && unroll == U) {                                               \
+    hipLaunchKernelGGL((k_lookup<GRID, PREC, L, U>), grid, block, 0, s, t, a); \
+    return hipGetLastError();                                                  \
   }
-  return hipGetLastError();
+  XS_CASE(1, 1)
+  XS_CASE(2, 1)
+  XS_CASE(3, 1)
+  XS_CASE(4, 1)
+  XS_CASE(5, 1)
+  XS_CASE(6, 1)
+  XS_CASE(7, 1)
+  XS_CASE(8, 1)
+  XS_CASE(1, 2)
+  XS_CASE(2, 2)
+  XS_CASE(1, 4)
+  XS_CASE(2, 4)
+#undef XS_CASE
+  return hipErrorInvalidValue;
 }
 
 template <int GRID>
 hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
                               const LookupArgs& a, hipStream_t s) {
-  if (p.block_size > max_block_for_lpt(p.lookups_per_thread))
+  if (!variant_exists(p.lookups_per_thread, p.unroll) ||
+      p.block_size > max_block_for(p.lookups_per_thread, p.unroll))
     return hipErrorInvalidValue;
   const int64_t per_block = (int64_t)p.block_size * p.lookups_per_thread;
   const int64_t nb = (a.n + per_block - 1) / per_block;
@@ -384,8 +579,10 @@ hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
   if (nb > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nb), block((unsigned)p.block_size);
   if (p.precision == XS_FP64)
-    return launch_lpt<GRID, XS_FP64>(t, p.lookups_per_thread, grid, block, a, s);
-  return launch_lpt<GRID, XS_FP32>(t, p.lookups_per_thread, grid, block, a, s);
+    return launch_variant<GRID, XS_FP64>(t, p.lookups_per_thread, p.unroll,
+                                         grid, block, a, s);
+  return launch_variant<GRID, XS_FP32>(t, p.lookups_per_thread, p.unroll, grid,
+                                       block, a, s);
 }
 
 template <int GRID>

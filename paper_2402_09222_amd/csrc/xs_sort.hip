@@ -35,7 +35,9 @@ __device__ __forceinline__ uint32_t make_key(const SortKey& k, double e,
   }
   if (k.mat_bits) {
     const int32_t mm = m < 0 ? 0 : (m >= k.M ? k.M - 1 : m);
-    key |= (uint32_t)mm << k.e_bits;
+    const int rest = k.e_bits - k.band_bits;  // energy bits below the material
+    const uint32_t band = key >> rest, low = key & ((1u << rest) - 1u);
+    key = (band << (k.mat_bits + rest)) | ((uint32_t)mm << rest) | low;
   }
   if (k.flag_bit && inactive) key |= 1u << (k.mat_bits + k.e_bits);
   return key;

@@ -1,0 +1,498 @@
+// Autotuner for the lookup's launch and method parameters (xs_tune,
+// xs_tune_search, xs_set_tuned).
+//
+// The paper tunes OpenMC's particles in flight, hash-bin count, queue mode
+// and sorting threshold with ytopt (section 2.1): Bayesian optimisation with
+// a random-forest surrogate of the objective and the lower-confidence-bound
+// acquisition a(x) = mu(x) - kappa sigma(x) (Eq. 1, kappa = 1.96 by default),
+// evaluating one configuration at a time or a batch per refit (section 3,
+// Steps 1-5).  An evaluation that runs longer than 1.5x the baseline
+// runtime is stopped and the time-out value is recorded as its objective
+// (section 3, last paragraph).  Parameters that only matter under another
+// parameter's value are conditional (the paper's ConfigSpace condition, as
+// in section 5.2): the sort threshold is inactive without a sort.
+//
+// Here the space is the lookup's own: grid method x sort policy x block size
+// x (lookups per lane, nuclides in flight), with invalid combinations
+// removed.  For a fixed batch size the threshold only decides whether the
+// sort runs, which the sort policy NONE already expresses, so it is 0 for
+// every sorting candidate.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <vector>
+
+#include "xs_internal.h"
+
+namespace xs {
+namespace {
+
+// ---- the configuration space ---------------------------------------------
+
+constexpr int kNumFeatures = 12;
+
+struct Cand {
+  xs_params p;
+  float f[kNumFeatures];
+};
+
+int max_block(int lpt, int unroll) {
+  const int w = lpt * unroll;
+  return w <= 2 ? 1024 : (w <= 4 ? 512 : 256);
+}
+
+std::vector<Cand> enumerate_space(int precision, uint32_t grids,
+                                  uint32_t sorts) {
+  static const int kBlocks[] = {64, 128, 256, 512, 1024};
+  static const int kVariants[][2] = {{1, 1}, {2, 1}, {3, 1}, {4, 1}, {5, 1},
+                                     {6, 1}, {7, 1}, {8, 1}, {1, 2}, {2, 2},
+                                     {1, 4}, {2, 4}};
+  std::vector<Cand> out;
+  for (int g = 0; g < 3; ++g) {
+    if (!(grids >> g & 1u)) continue;
+    for (int s = 0; s < 5; ++s) {
+      if (!(sorts >> s & 1u)) continue;
+      for (int b : kBlocks) {
+        for (auto& v : kVariants) {
+          if (b > max_block(v[0], v[1])) continue;
+          Cand c{};
+          c.p.precision = precision;
+          c.p.grid = g;
+          c.p.sort = s;
+          c.p.block_size = b;
+          c.p.lookups_per_thread = v[0];
+          c.p.unroll = v[1];
+          c.p.lds_stage = 0;
+          c.p.sort_threshold =
+              s == XS_SORT_NONE ? std::numeric_limits<int64_t>::max() : 0;
+          c.p.queue = XS_QUEUE_COMPACT;
+          for (int i = 0; i < 3; ++i) c.f[i] = g == i ? 1.f : 0.f;
+          for (int i = 0; i < 5; ++i) c.f[3 + i] = s == i ? 1.f : 0.f;
+          c.f[8] = std::log2((float)b);
+          c.f[9] = (float)v[0];
+          c.f[10] = (float)v[1];
+          c.f[11] = (float)(v[0] * v[1]);
+          out.push_back(c);
+        }
+      }
+    }
+  }
+  return out;
+}
+
+// ---- random numbers (SplitMix64) -------------------------------------------
+
+struct Rng {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  size_t below(size_t n) { return (size_t)(next() % n); }
+};
+
+// ---- random-forest regressor ---------------------------------------------
+//
+// Bootstrap-sampled CART trees grown on squared error, each split chosen
+// among a random subset of the features (8 of 12; nodes under 4 samples stay
+// leaves); the forest's mean is the prediction and the spread of the trees'
+// predictions its uncertainty.
+
+struct Node {
+  int feature = -1;  // -1: leaf
+  float threshold = 0.f;
+  int left = -1, right = -1;
+  double value = 0.0;
+};
+
+struct Tree {
+  std::vector<Node> nodes;
+  double predict(const float* x) const {
+    int i = 0;
+    while (nodes[i].feature >= 0)
+      i = x[nodes[i].feature] <= nodes[i].threshold ? nodes[i].left
+                                                     : nodes[i].right;
+    return nodes[i].value;
+  }
+};
+
+class Forest {
+ public:
+  Forest(int trees, int max_features, int max_depth, uint64_t seed)
+      : trees_(trees), max_features_(max_features), max_depth_(max_depth),
+        rng_{seed} {}
+
+  void fit(const std::vector<const float*>& X, const std::vector<double>& y) {
+    forest_.assign(trees_, Tree{});
+    const size_t n = X.size();
+    for (auto& t : forest_) {
+      std::vector<size_t> idx(n);
+      for (auto& i : idx) i = rng_.below(n);
+      grow(t, X, y, idx, 0);
+    }
+  }
+
+  void predict(const float* x, double* mean, double* sd) const {
+    double s = 0, s2 = 0;
+    for (auto& t : forest_) {
+      const double v = t.predict(x);
+      s += v;
+      s2 += v * v;
+    }
+    const double m = s / forest_.size();
+    *mean = m;
+    *sd = std::sqrt(std::max(0.0, s2 / forest_.size() - m * m));
+  }
+
+ private:
+  int grow(Tree& t, const std::vector<const float*>& X,
+           const std::vector<double>& y, std::vector<size_t>& idx, int depth) {
+    const int id = (int)t.nodes.size();
+    t.nodes.emplace_back();
+    double sum = 0;
+    for (size_t i : idx) sum += y[i];
+    t.nodes[id].value = sum / idx.size();
+    if (depth >= max_depth_ || idx.size() < 4) return id;
+
+    // Random feature subset.
+    int feats[kNumFeatures];
+    std::iota(feats, feats + kNumFeatures, 0);
+    for (int i = kNumFeatures - 1; i > 0; --i)
+      std::swap(feats[i], feats[rng_.below(i + 1)]);
+
+    double best_sse = std::numeric_limits<double>::infinity();
+    int best_f = -1;
+    float best_thr = 0.f;
+    std::vector<std::pair<float, double>> v(idx.size());
+    for (int fi = 0; fi < max_features_; ++fi) {
+      const int f = feats[fi];
+      for (size_t i = 0; i < idx.size(); ++i) v[i] = {X[idx[i]][f], y[idx[i]]};
+      std::sort(v.begin(), v.end(),
+                [](auto& a, auto& b) { return a.first < b.first; });
+      double ls = 0, ls2 = 0, rs = 0, rs2 = 0;
+      for (auto& e : v) {
+        rs += e.second;
+        rs2 += e.second * e.second;
+      }
+      for (size_t i = 0; i + 1 < v.size(); ++i) {
+        ls += v[i].second;
+        ls2 += v[i].second * v[i].second;
+        rs -= v[i].second;
+        rs2 -= v[i].second * v[i].second;
+        if (v[i].first == v[i + 1].first) continue;
+        const double nl = i + 1, nr = v.size() - i - 1;
+        const double sse = (ls2 - ls * ls / nl) + (rs2 - rs * rs / nr);
+        if (sse < best_sse) {
+          best_sse = sse;
+          best_f = f;
+          best_thr = 0.5f * (v[i].first + v[i + 1].first);
+        }
+      }
+    }
+    if (best_f < 0) return id;
+    std::vector<size_t> li, ri;
+    for (size_t i : idx) (X[i][best_f] <= best_thr ? li : ri).push_back(i);
+    if (li.empty() || ri.empty()) return id;
+    const int l = grow(t, X, y, li, depth + 1);
+    const int r = grow(t, X, y, ri, depth + 1);
+    t.nodes[id].feature = best_f;
+    t.nodes[id].threshold = best_thr;
+    t.nodes[id].left = l;
+    t.nodes[id].right = r;
+    return id;
+  }
+
+  int trees_, max_features_, max_depth_;
+  Rng rng_;
+  std::vector<Tree> forest_;
+};
+
+bool same_choice(const xs_params& a, const xs_params& b) {
+  return a.grid == b.grid && a.sort == b.sort && a.block_size == b.block_size &&
+         a.lookups_per_thread == b.lookups_per_thread && a.unroll == b.unroll;
+}
+
+// ---- the search ---------------------------------------------------------------
+
+struct Search {
+  const xs_tune_config& cfg;
+  xs_eval_fn eval;
+  void* user;
+  std::vector<Cand> space;
+  std::vector<double> obj;  // log(ms) objective per candidate (NaN = not run)
+  std::vector<int> order;   // evaluation order
+  double cutoff = std::numeric_limits<double>::infinity();
+  int cut = 0;
+  int best = -1;
+  int best_eval = 0;
+
+  xs_status run_one(int c) {
+    double ms = 0;
+    const xs_status st = eval(&space[c].p, cutoff, &ms, user);
+    if (st != XS_OK) return st;
+    if (!(ms > 0) || !std::isfinite(ms)) ms = cutoff;
+    if (ms > cutoff) {
+      ms = cutoff;  // the time-out value is the recorded objective
+      ++cut;
+    }
+    obj[c] = std::log(ms);
+    order.push_back(c);
+    if (best < 0 || obj[c] < obj[best]) {
+      best = c;
+      best_eval = (int)order.size();
+    }
+    return XS_OK;
+  }
+};
+
+}  // namespace
+}  // namespace xs
+
+using namespace xs;
+
+extern "C" {
+
+xs_status xs_tune_config_default(xs_tune_config* c) {
+  clear_error();
+  if (!c) return fail(XS_EINVAL, "config is NULL");
+  std::memset(c, 0, sizeof(*c));
+  c->precision = XS_FP64;
+  c->strategy = XS_TUNE_FOREST;
+  c->max_evals = 48;
+  c->init_samples = 10;
+  c->batch = 1;
+  c->reps = 5;
+  c->warmup = 1;
+  c->timeout_factor = 1.5;
+  c->kappa = 1.96;
+  c->seed = 1234;
+  c->grid_mask = 0;
+  c->sort_mask = 0;
+  return XS_OK;
+}
+
+xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
+                         xs_eval_fn eval, void* user, xs_tune_result* result) {
+  clear_error();
+  if (!cfg || !eval || !result)
+    return fail(XS_EINVAL, "config, evaluator and result must not be NULL");
+  if (cfg->precision != XS_FP64 && cfg->precision != XS_FP32)
+    return fail(XS_EINVAL, "precision must be XS_FP64 or XS_FP32");
+  if (cfg->strategy != XS_TUNE_EXHAUSTIVE && cfg->strategy != XS_TUNE_FOREST)
+    return fail(XS_EINVAL, "unknown strategy %d", cfg->strategy);
+  if (cfg->kappa < 0) return fail(XS_EINVAL, "kappa must be >= 0");
+  if (cfg->reserved != 0) return fail(XS_EINVAL, "reserved field must be 0");
+  if (cfg->batch < 0) return fail(XS_EINVAL, "batch must be >= 0");
+  const uint32_t grids = (cfg->grid_mask ? cfg->grid_mask : 7u) & built_grids;
+  const uint32_t sorts = cfg->sort_mask ? cfg->sort_mask : 31u;
+  Search S{*cfg, eval, user, enumerate_space(cfg->precision, grids, sorts)};
+  const int N = (int)S.space.size();
+  if (N == 0) return fail(XS_EINVAL, "the parameter space is empty");
+  S.obj.assign(N, std::numeric_limits<double>::quiet_NaN());
+
+  // Baseline: the library default (hash grid if built, banded sort, block
+  // 256, one lookup per lane, two nuclides in flight), else the first
+  // candidate.
+  xs_params base{};
+  base.grid = (grids & 2u) ? XS_GRID_HASH : ((grids & 1u) ? XS_GRID_NUCLIDE
+                                                          : XS_GRID_UNIONIZED);
+  base.sort = (sorts & 16u) ? XS_SORT_BAND_MATERIAL : XS_SORT_NONE;
+  base.block_size = 256;
+  base.lookups_per_thread = 1;
+  base.unroll = 2;
+  int b0 = 0;
+  for (int i = 0; i < N; ++i)
+    if (same_choice(S.space[i].p, base)) b0 = i;
+  if (xs_status st = S.run_one(b0)) return st;
+  if (cfg->timeout_factor > 0)
+    S.cutoff = cfg->timeout_factor * std::exp(S.obj[b0]);
+
+  const int budget = cfg->strategy == XS_TUNE_EXHAUSTIVE || cfg->max_evals <= 0
+                         ? N
+                         : std::min(N, cfg->max_evals);
+  Rng rng{cfg->seed};
+  if (cfg->strategy == XS_TUNE_EXHAUSTIVE) {
+    for (int i = 0; i < N && (int)S.order.size() < budget; ++i)
+      if (std::isnan(S.obj[i]))
+        if (xs_status st = S.run_one(i)) return st;
+  } else {
+    // Initial random configurations, then surrogate-guided batches.
+    const int init = std::max(1, std::min(cfg->init_samples, budget));
+    while ((int)S.order.size() < init) {
+      const int c = (int)rng.below(N);
+      if (!std::isnan(S.obj[c])) {
+        bool left = false;
+        for (int i = 0; i < N; ++i) left = left || std::isnan(S.obj[i]);
+        if (!left) break;
+        continue;
+      }
+      if (xs_status st = S.run_one(c)) return st;
+    }
+    const int batch = std::max(1, cfg->batch);
+    while ((int)S.order.size() < budget) {
+      std::vector<const float*> X;
+      std::vector<double> y;
+      for (int c : S.order) {
+        X.push_back(S.space[c].f);
+        y.push_back(S.obj[c]);
+      }
+      Forest forest(64, 8, 12, rng.next());
+      forest.fit(X, y);
+      std::vector<std::pair<double, int>> acq;
+      for (int i = 0; i < N; ++i) {
+        if (!std::isnan(S.obj[i])) continue;
+        double mu, sd;
+        forest.predict(S.space[i].f, &mu, &sd);
+        acq.push_back({mu - cfg->kappa * sd, i});
+      }
+      if (acq.empty()) break;
+      std::sort(acq.begin(), acq.end());
+      const int take = std::min<int>({batch, (int)acq.size(),
+                                      budget - (int)S.order.size()});
+      for (int k = 0; k < take; ++k)
+        if (xs_status st = S.run_one(acq[k].second)) return st;
+    }
+  }
+  xs_tune_result r{};
+  r.best = S.space[S.best].p;
+  r.best_ms = std::exp(S.obj[S.best]);
+  r.baseline = S.space[b0].p;
+  r.baseline_ms = std::exp(S.obj[b0]);
+  r.evaluated = (int)S.order.size();
+  r.cut = S.cut;
+  r.space_size = N;
+  r.best_eval = S.best_eval;
+  *result = r;
+  return XS_OK;
+}
+
+}  // extern "C"
+
+namespace xs {
+namespace {
+
+// Times xs_lookup_batch with HIP events on the caller's stream: `warmup`
+// untimed runs, then up to `reps` timed runs (best kept); stops after the
+// first timed run when it already exceeds the cut-off.
+struct DeviceEval {
+  xs_tables_t h;
+  int64_t n;
+  const double* E;
+  const int32_t* mat;
+  void* out;
+  void* ws;
+  size_t ws_bytes;
+  hipStream_t s;
+  int warmup, reps;
+  hipEvent_t a, b;
+};
+
+int32_t device_eval(const xs_params* p, double cutoff_ms, double* ms,
+                    void* user) {
+  DeviceEval& d = *(DeviceEval*)user;
+  for (int i = 0; i < d.warmup; ++i)
+    if (xs_status st = xs_lookup_batch(d.h, d.n, d.E, d.mat, d.out, p, d.ws,
+                                       d.ws_bytes, d.s))
+      return st;
+  double best = std::numeric_limits<double>::infinity();
+  for (int i = 0; i < std::max(1, d.reps); ++i) {
+    XS_HIP(hipEventRecord(d.a, d.s));
+    if (xs_status st = xs_lookup_batch(d.h, d.n, d.E, d.mat, d.out, p, d.ws,
+                                       d.ws_bytes, d.s))
+      return st;
+    XS_HIP(hipEventRecord(d.b, d.s));
+    XS_HIP(hipEventSynchronize(d.b));
+    float t = 0;
+    XS_HIP(hipEventElapsedTime(&t, d.a, d.b));
+    best = std::min(best, (double)t);
+    if (best > cutoff_ms) break;
+  }
+  *ms = best;
+  return XS_OK;
+}
+
+int bucket_of(int64_t n) {
+  return n > 0 ? 63 - __builtin_clzll((unsigned long long)n) : 0;
+}
+
+}  // namespace
+}  // namespace xs
+
+extern "C" {
+
+xs_status xs_tune(xs_tables_t h, int64_t n, const double* d_E,
+                  const int32_t* d_mat, void* d_out, void* d_ws,
+                  size_t ws_bytes, void* stream, const xs_tune_config* cfg,
+                  xs_tune_result* result) {
+  clear_error();
+  if (!h) return fail(XS_EINVAL, "table handle is NULL");
+  if (!cfg || !result) return fail(XS_EINVAL, "config and result must not be NULL");
+  if (n <= 0 || n > 0x7fffffffLL) return fail(XS_EINVAL, "n out of range");
+  if (!d_E || !d_mat || !d_out) return fail(XS_EINVAL, "a pointer is NULL");
+  {
+    // The workspace must fit the most demanding candidate (a sort).
+    xs_params probe;
+    xs_params_default(&probe, cfg->precision);
+    probe.sort = XS_SORT_BAND_MATERIAL;
+    probe.sort_threshold = 0;
+    probe.grid = XS_GRID_NUCLIDE;
+    size_t need = 0;
+    if (xs_status st = xs_workspace_size(h, n, &probe, &need)) return st;
+    if (!d_ws || ws_bytes < need)
+      return fail(XS_EWORKSPACE, "tuning needs a workspace of %zu bytes", need);
+  }
+  uint32_t built = 1u;
+  if (h->d.B > 0) built |= 2u;
+  if (h->d.U > 0) built |= 4u;
+  if (cfg->precision == XS_FP32 && !h->d.rec32)
+    return fail(XS_ENOTBUILT, "FP32 tables were not built");
+  DeviceEval d{h, n, d_E, d_mat, d_out, d_ws, ws_bytes, (hipStream_t)stream,
+               std::max(0, cfg->warmup), std::max(1, cfg->reps), nullptr,
+               nullptr};
+  XS_HIP(hipEventCreate(&d.a));
+  XS_HIP(hipEventCreate(&d.b));
+  xs_tune_result r{};
+  const xs_status st = xs_tune_search(built, cfg, device_eval, &d, &r);
+  (void)hipEventDestroy(d.a);
+  (void)hipEventDestroy(d.b);
+  if (st != XS_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->tuned[cfg->precision][bucket_of(n)] = r.best;
+    h->tuned_valid[cfg->precision][bucket_of(n)] = true;
+  }
+  *result = r;
+  return XS_OK;
+}
+
+xs_status xs_set_tuned(xs_tables_t h, int64_t n, const xs_params* p) {
+  clear_error();
+  if (!h) return fail(XS_EINVAL, "table handle is NULL");
+  if (n <= 0) return fail(XS_EINVAL, "n must be > 0");
+  if (!p) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    for (int prec = 0; prec < 2; ++prec)
+      for (int b = 0; b < kBuckets; ++b) h->tuned_valid[prec][b] = false;
+    return XS_OK;
+  }
+  // Must be complete and valid on its own (no automatic fields).
+  if (p->grid == XS_AUTO || p->sort == XS_AUTO || p->block_size <= 0 ||
+      p->lookups_per_thread <= 0 || p->lds_stage == XS_AUTO ||
+      p->sort_threshold < 0 || p->queue == XS_AUTO || p->unroll <= 0)
+    return fail(XS_EINVAL, "tuned parameters must not contain automatic fields");
+  xs_params checked;
+  if (xs_status st = xs_resolve_params(h, n, p, &checked)) return st;
+  std::lock_guard<std::mutex> lk(h->mu);
+  h->tuned[p->precision][bucket_of(n)] = checked;
+  h->tuned_valid[p->precision][bucket_of(n)] = true;
+  return XS_OK;
+}
+
+}  // extern "C"

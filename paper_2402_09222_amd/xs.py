@@ -22,6 +22,7 @@ XS_CHANNELS = 5
 XS_GRID_NUCLIDE, XS_GRID_HASH, XS_GRID_UNIONIZED = 0, 1, 2
 XS_FP64, XS_FP32 = 0, 1
 XS_SORT_NONE, XS_SORT_MATERIAL, XS_SORT_ENERGY, XS_SORT_MATERIAL_ENERGY = 0, 1, 2, 3
+XS_SORT_BAND_MATERIAL = 4
 XS_QUEUE_COMPACT, XS_QUEUE_PREDICATED = 0, 1
 XS_BUILD_FP32, XS_BUILD_HASH, XS_BUILD_UNIONIZED = 1, 2, 4
 INT64_MAX = (1 << 63) - 1
@@ -29,7 +30,8 @@ INT64_MAX = (1 << 63) - 1
 GRIDS = {"nuclide": XS_GRID_NUCLIDE, "hash": XS_GRID_HASH,
          "unionized": XS_GRID_UNIONIZED}
 SORTS = {"none": XS_SORT_NONE, "material": XS_SORT_MATERIAL,
-         "energy": XS_SORT_ENERGY, "material_energy": XS_SORT_MATERIAL_ENERGY}
+         "energy": XS_SORT_ENERGY, "material_energy": XS_SORT_MATERIAL_ENERGY,
+         "band_material": XS_SORT_BAND_MATERIAL}
 
 
 class XsError(RuntimeError):
@@ -64,11 +66,11 @@ class xs_params(ctypes.Structure):
         ("lds_stage", ctypes.c_int32),
         ("sort_threshold", ctypes.c_int64),
         ("queue", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("unroll", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class xs_table_info_t(ctypes.Structure):
@@ -109,6 +111,49 @@ class xs_profile_t(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class xs_tune_config(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("strategy", ctypes.c_int32),
+        ("max_evals", ctypes.c_int32),
+        ("init_samples", ctypes.c_int32),
+        ("batch", ctypes.c_int32),
+        ("reps", ctypes.c_int32),
+        ("warmup", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("timeout_factor", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("grid_mask", ctypes.c_uint32),
+        ("sort_mask", ctypes.c_uint32),
+    ]
+
+
+class xs_tune_result(ctypes.Structure):
+    _fields_ = [
+        ("best", xs_params),
+        ("best_ms", ctypes.c_double),
+        ("baseline", xs_params),
+        ("baseline_ms", ctypes.c_double),
+        ("evaluated", ctypes.c_int32),
+        ("cut", ctypes.c_int32),
+        ("space_size", ctypes.c_int32),
+        ("best_eval", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {"best": self.best.as_dict(), "best_ms": self.best_ms,
+                "baseline": self.baseline.as_dict(),
+                "baseline_ms": self.baseline_ms, "evaluated": self.evaluated,
+                "cut": self.cut, "space_size": self.space_size,
+                "best_eval": self.best_eval}
+
+
+XS_TUNE_EXHAUSTIVE, XS_TUNE_FOREST = 0, 1
+EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(xs_params),
+                           ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                           ctypes.c_void_p)
+
 _lib = None
 
 
@@ -144,6 +189,12 @@ def load_library(path: str = LIB_PATH):
         "xs_lookup_indices": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
         "xs_profile_begin": ([vp], i32),
         "xs_profile_end": ([vp, P(xs_profile_t)], i32),
+        "xs_tune_config_default": ([P(xs_tune_config)], i32),
+        "xs_tune_search": ([ctypes.c_uint32, P(xs_tune_config), EVAL_FN, vp,
+                            P(xs_tune_result)], i32),
+        "xs_tune": ([vp, i64, vp, vp, vp, vp, sz, vp, P(xs_tune_config),
+                     P(xs_tune_result)], i32),
+        "xs_set_tuned": ([vp, i64, P(xs_params)], i32),
         "xs_status_string": ([i32], ctypes.c_char_p),
         "xs_last_error": ([], ctypes.c_char_p),
     }
@@ -179,13 +230,13 @@ def _stream_ptr(stream, device=None):
 
 def make_params(precision=XS_FP64, grid=XS_AUTO, sort=XS_AUTO, block_size=0,
                 lookups_per_thread=0, lds_stage=XS_AUTO, sort_threshold=-1,
-                queue=XS_AUTO) -> xs_params:
+                queue=XS_AUTO, unroll=0) -> xs_params:
     if isinstance(grid, str):
         grid = GRIDS[grid]
     if isinstance(sort, str):
         sort = SORTS[sort]
     return xs_params(precision, grid, sort, block_size, lookups_per_thread,
-                     lds_stage, sort_threshold, queue, 0)
+                     lds_stage, sort_threshold, queue, unroll)
 
 
 class Tables:
@@ -387,3 +438,70 @@ def xs_profile_end(tables: Tables) -> dict:
     _check(load_library().xs_profile_end(tables.handle, ctypes.byref(p)),
            "xs_profile_end")
     return p.as_dict()
+
+
+def xs_tune_config_default(**over) -> xs_tune_config:
+    """Default tuner configuration with fields overridden by keyword."""
+    c = xs_tune_config()
+    _check(load_library().xs_tune_config_default(ctypes.byref(c)),
+           "xs_tune_config_default")
+    for k, v in over.items():
+        setattr(c, k, v)
+    return c
+
+
+def xs_tune_search(built_grids: int, cfg: xs_tune_config, evaluate) -> xs_tune_result:
+    """Run the search with a Python evaluator evaluate(params, cutoff_ms) ->
+    milliseconds (no device needed)."""
+    err = []
+
+    def cb(p, cutoff, ms, user):
+        try:
+            ms[0] = float(evaluate(p.contents, cutoff))
+            return XS_OK
+        except Exception as e:  # report through the status code
+            err.append(e)
+            return XS_EINVAL
+
+    fn = EVAL_FN(cb)
+    r = xs_tune_result()
+    st = load_library().xs_tune_search(built_grids, ctypes.byref(cfg), fn,
+                                       None, ctypes.byref(r))
+    if err:
+        raise err[0]
+    _check(st, "xs_tune_search")
+    return r
+
+
+def xs_tune(tables: Tables, E, mat, cfg: xs_tune_config = None, out=None,
+            workspace=None, stream=None) -> xs_tune_result:
+    """Tune xs_lookup_batch for len(E) lookups on these queries and record the
+    winner in the handle."""
+    import torch
+    _check_queries(E, mat)
+    n = E.numel()
+    if cfg is None:
+        cfg = xs_tune_config_default()
+    dt = torch.float64 if cfg.precision == XS_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((n, XS_CHANNELS), dtype=dt, device=E.device)
+    if workspace is None:
+        nb = xs_workspace_size(tables, n, make_params(
+            cfg.precision, grid=XS_GRID_NUCLIDE, sort=XS_SORT_BAND_MATERIAL,
+            sort_threshold=0))
+        keep, ws, nb = _workspace(nb, E.device)
+    else:
+        keep, ws, nb = workspace
+    r = xs_tune_result()
+    _check(load_library().xs_tune(
+        tables.handle, n, ctypes.c_void_p(E.data_ptr()),
+        ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(out.data_ptr()), ws,
+        nb, _stream_ptr(stream, E.device), ctypes.byref(cfg), ctypes.byref(r)),
+        "xs_tune")
+    return r
+
+
+def xs_set_tuned(tables: Tables, n: int, params: xs_params = None):
+    _check(load_library().xs_set_tuned(
+        tables.handle, n, ctypes.byref(params) if params is not None else None),
+        "xs_set_tuned")

@@ -71,7 +71,7 @@ def test_params_default(lib):
     assert p.precision == xs.XS_FP32
     assert p.grid == xs.XS_AUTO and p.sort == xs.XS_AUTO
     assert p.block_size == 0 and p.lookups_per_thread == 0
-    assert p.sort_threshold == -1 and p.reserved == 0
+    assert p.sort_threshold == -1 and p.unroll == 0
     with pytest.raises(xs.XsError) as e:
         xs.xs_params_default(7)
     assert e.value.status == xs.XS_EINVAL

@@ -69,7 +69,8 @@ def test_plain_fp64_samples(full):
 
 
 @pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
-@pytest.mark.parametrize("sort", ["none", "material", "energy", "material_energy"])
+@pytest.mark.parametrize("sort", ["none", "material", "energy", "material_energy",
+                                  "band_material"])
 def test_fp64_grids_and_sorts_identical(full, grid, sort):
     say("fp64 full size", grid, sort)
     if "out64" not in full:
@@ -94,7 +95,11 @@ def test_fp32_samples_and_bound(full, grid):
         assert rel.max() <= 2e-6
     for k in (dict(sort="none", block_size=1024, lookups_per_thread=1),
               dict(sort="material", sort_threshold=0, block_size=512,
-                   lookups_per_thread=4)):
+                   lookups_per_thread=4),
+              dict(sort="band_material", sort_threshold=0, block_size=256,
+                   lookups_per_thread=1, unroll=4),
+              dict(sort="band_material", sort_threshold=0, block_size=512,
+                   lookups_per_thread=2, unroll=2)):
         o2 = run(full, precision=xs.XS_FP32, grid=grid, **k).cpu().numpy()
         assert np.array_equal(o2, o), k
 

@@ -95,16 +95,23 @@ def test_cfg1_indices_bit_exact(cfg1, grid):
 
 
 KNOBS = [
-    dict(sort="none", block_size=64, lookups_per_thread=1),
-    dict(sort="none", block_size=1024, lookups_per_thread=2),
+    dict(sort="none", block_size=64, lookups_per_thread=1, unroll=1),
+    dict(sort="none", block_size=1024, lookups_per_thread=2, unroll=1),
     dict(sort="material", sort_threshold=0, block_size=128, lookups_per_thread=3),
     dict(sort="energy", sort_threshold=0, block_size=512, lookups_per_thread=4),
     dict(sort="material_energy", sort_threshold=0, block_size=256,
          lookups_per_thread=8),
+    dict(sort="band_material", sort_threshold=0, block_size=256,
+         lookups_per_thread=1, unroll=4),
+    dict(sort="band_material", sort_threshold=0, block_size=256,
+         lookups_per_thread=2, unroll=2),
+    dict(sort="none", block_size=1024, lookups_per_thread=1, unroll=2),
     dict(sort="material_energy", sort_threshold=xs.INT64_MAX, block_size=192,
          lookups_per_thread=5),
-    dict(sort="material_energy", sort_threshold=20000, block_size=64,
+    dict(sort="band_material", sort_threshold=20000, block_size=64,
          lookups_per_thread=7),
+    dict(sort="energy", sort_threshold=0, block_size=256, lookups_per_thread=2,
+         unroll=4),
 ]
 
 
@@ -125,6 +132,7 @@ def test_default_params(cfg1):
     assert np.array_equal(out.cpu().numpy(), cfg1["ref"])
     p = xs.xs_resolve_params(cfg1["h"], 100000)
     assert p.grid == xs.XS_GRID_HASH and p.block_size == 256
+    assert p.sort == xs.XS_SORT_BAND_MATERIAL and p.unroll == 2
 
 
 def test_edge_queries(cfg1):
@@ -201,7 +209,7 @@ def test_hash_bins_indices(cfg1, bins):
 
 
 @pytest.mark.parametrize("queue", [xs.XS_QUEUE_COMPACT, xs.XS_QUEUE_PREDICATED])
-@pytest.mark.parametrize("sort", ["none", "material_energy"])
+@pytest.mark.parametrize("sort", ["none", "material_energy", "band_material"])
 def test_active_mask(cfg1, queue, sort):
     """Inactive slots keep their sentinel; active ones match the oracle."""
     n = len(cfg1["q"])
@@ -228,11 +236,14 @@ def test_errors_from_device_calls(cfg1):
         xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
                            params=xs.make_params(block_size=100))
     assert e.value.status == xs.XS_EINVAL
-    with pytest.raises(xs.XsError) as e:
-        xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
-                           params=xs.make_params(block_size=1024,
-                                                 lookups_per_thread=5))
-    assert e.value.status == xs.XS_EINVAL
+    for bad in (dict(block_size=1024, lookups_per_thread=5),
+                dict(block_size=1024, lookups_per_thread=2, unroll=2),
+                dict(lookups_per_thread=3, unroll=2), dict(unroll=3),
+                dict(sort=5), dict(grid=3), dict(lds_stage=2)):
+        with pytest.raises(xs.XsError) as e:
+            xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
+                               params=xs.make_params(**bad))
+        assert e.value.status == xs.XS_EINVAL, bad
     small = xs.xs_create_tables(cfg1["t"], 0, 0)
     for p in (xs.make_params(grid="hash"), xs.make_params(grid="unionized"),
               xs.make_params(precision=xs.XS_FP32, grid="nuclide")):

@@ -1,0 +1,182 @@
+"""The tuner's search without a device: a mock evaluator stands in for the
+GPU and returns synthetic runtimes (a mock clock).
+
+Checks: only valid configurations are proposed; the sort threshold is
+conditional on the sort policy (paper section 5.2's EqualsCondition
+pattern); exhaustive search returns the optimum; a configuration slower than
+1.5x the baseline is cut and scored at the time-out (section 3); the forest
+search (section 2.1, Eq. 1) finds near-optimal configurations in a small
+budget and beats random choice; masks and evaluator errors are honoured.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2402_09222_amd import xs
+
+INT64_MAX = (1 << 63) - 1
+BLOCKS = (64, 128, 256, 512, 1024)
+
+
+def max_block(lpt, unroll):
+    w = lpt * unroll
+    return 1024 if w <= 2 else (512 if w <= 4 else 256)
+
+
+def cost(p):
+    """A synthetic runtime with interactions: sorted unionized with two
+    nuclides in flight and mid-size blocks is best."""
+    grid = (4.0, 2.0, 1.0)[p.grid]
+    sort = (3.0, 1.6, 2.2, 1.4, 1.0)[p.sort]
+    blk = 1.0 + 0.15 * abs(math.log2(p.block_size) - 8)
+    w = p.lookups_per_thread * p.unroll
+    ilp = 1.0 + 0.08 * abs(w - 2) + (0.3 if p.grid == 0 and p.unroll > 1 else 0)
+    return grid * sort * blk * ilp
+
+
+class Recorder:
+    def __init__(self, fn=cost):
+        self.fn = fn
+        self.calls = []
+        self.cutoffs = []
+
+    def __call__(self, p, cutoff):
+        self.calls.append(dict(grid=p.grid, sort=p.sort, bs=p.block_size,
+                               lpt=p.lookups_per_thread, u=p.unroll,
+                               thr=p.sort_threshold, lds=p.lds_stage,
+                               prec=p.precision))
+        self.cutoffs.append(cutoff)
+        return self.fn(p)
+
+
+def all_valid(calls):
+    for c in calls:
+        assert c["bs"] in BLOCKS
+        assert 1 <= c["lpt"] <= 8 and c["u"] in (1, 2, 4)
+        assert c["u"] == 1 or c["lpt"] <= 2
+        assert c["bs"] <= max_block(c["lpt"], c["u"])
+        assert c["lds"] == 0
+        # conditional parameter: the threshold only means something when a
+        # sort is selected; it is never varied within a policy
+        assert c["thr"] == (INT64_MAX if c["sort"] == 0 else 0)
+
+
+def test_exhaustive_finds_optimum():
+    rec = Recorder()
+    cfg = xs.xs_tune_config_default(strategy=xs.XS_TUNE_EXHAUSTIVE,
+                                    timeout_factor=0.0)
+    r = xs.xs_tune_search(7, cfg, rec)
+    assert r.evaluated == r.space_size == len(rec.calls)
+    all_valid(rec.calls)
+    keys = {(c["grid"], c["sort"], c["bs"], c["lpt"], c["u"]) for c in rec.calls}
+    assert len(keys) == len(rec.calls)  # no configuration twice
+    best = min(cost_of(c) for c in rec.calls)
+    assert r.best_ms == pytest.approx(best)
+    assert r.best.grid == 2 and r.best.sort == 4 and r.best.block_size == 256
+    assert r.best.lookups_per_thread * r.best.unroll == 2
+    assert r.cut == 0
+
+
+def cost_of(c):
+    p = xs.make_params(c["prec"], grid=c["grid"], sort=c["sort"],
+                       block_size=c["bs"], lookups_per_thread=c["lpt"],
+                       unroll=c["u"])
+    return cost(p)
+
+
+def test_space_size_matches_enumeration():
+    n = 0
+    for lpt, u in [(l, 1) for l in range(1, 9)] + [(1, 2), (2, 2), (1, 4), (2, 4)]:
+        n += sum(1 for b in BLOCKS if b <= max_block(lpt, u))
+    for grids, mult in ((7, 3), (1, 1), (5, 2)):
+        cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0)
+        r = xs.xs_tune_search(grids, cfg, Recorder())
+        assert r.space_size == n * 5 * mult
+
+
+def test_timeout_rule_cuts_and_scores_at_cutoff():
+    """Baseline first; every later configuration slower than 1.5x the
+    baseline is cut and recorded at exactly the time-out value."""
+    rec = Recorder()
+    cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=1.5)
+    r = xs.xs_tune_search(7, cfg, rec)
+    base = rec.calls[0]
+    assert (base["grid"], base["sort"], base["bs"], base["lpt"], base["u"]) == \
+        (1, 4, 256, 1, 2)
+    assert math.isinf(rec.cutoffs[0])
+    t0 = cost_of(base)
+    assert r.baseline_ms == pytest.approx(t0)
+    assert all(c == pytest.approx(1.5 * t0) for c in rec.cutoffs[1:])
+    slow = sum(1 for c in rec.calls[1:] if cost_of(c) > 1.5 * t0)
+    assert r.cut == slow > 0
+
+
+def test_forest_beats_random_search():
+    """With 40 of ~690 evaluations the surrogate-guided search lands within
+    10% of the optimum for every seed, within 3% on average, and on average
+    no worse than the best of 40 random configurations."""
+    opt = None
+    forest, rand = [], []
+    for seed in range(6):
+        cfg = xs.xs_tune_config_default(strategy=xs.XS_TUNE_FOREST,
+                                        max_evals=40, seed=seed,
+                                        timeout_factor=0.0)
+        rec = Recorder()
+        r = xs.xs_tune_search(7, cfg, rec)
+        assert r.evaluated == 40 == len(rec.calls)
+        all_valid(rec.calls)
+        forest.append(r.best_ms)
+        if opt is None:
+            ex = xs.xs_tune_search(7, xs.xs_tune_config_default(
+                strategy=0, timeout_factor=0.0), Recorder())
+            opt = ex.best_ms
+            space = ex.space_size
+        rng = np.random.default_rng(seed)
+        allc = Recorder()
+        xs.xs_tune_search(7, xs.xs_tune_config_default(
+            strategy=0, timeout_factor=0.0), allc)
+        costs = np.array([cost_of(c) for c in allc.calls])
+        rand.append(costs[rng.choice(space, 40, replace=False)].min())
+    assert max(forest) <= 1.10 * opt
+    assert np.mean(forest) <= 1.03 * opt
+    assert np.mean(forest) <= np.mean(rand)
+
+
+def test_batch_proposals_and_determinism():
+    cfg = xs.xs_tune_config_default(strategy=1, max_evals=30, batch=4, seed=9,
+                                    timeout_factor=0.0)
+    a, b = Recorder(), Recorder()
+    ra = xs.xs_tune_search(7, cfg, a)
+    rb = xs.xs_tune_search(7, cfg, b)
+    assert a.calls == b.calls and ra.best_ms == rb.best_ms
+    assert ra.evaluated == 30
+
+
+def test_masks():
+    rec = Recorder()
+    cfg = xs.xs_tune_config_default(strategy=0, grid_mask=1, sort_mask=1 | 16,
+                                    timeout_factor=0.0)
+    xs.xs_tune_search(7, cfg, rec)
+    assert {c["grid"] for c in rec.calls} == {0}
+    assert {c["sort"] for c in rec.calls} == {0, 4}
+    rec = Recorder()
+    xs.xs_tune_search(2, xs.xs_tune_config_default(strategy=0,
+                                                   timeout_factor=0.0), rec)
+    assert {c["grid"] for c in rec.calls} == {1}
+    rec = Recorder()
+    xs.xs_tune_search(7, xs.xs_tune_config_default(strategy=0, precision=1,
+                                                   timeout_factor=0.0), rec)
+    assert {c["prec"] for c in rec.calls} == {1}
+
+
+def test_errors():
+    def boom(p, cutoff):
+        raise RuntimeError("device lost")
+    with pytest.raises(RuntimeError):
+        xs.xs_tune_search(7, xs.xs_tune_config_default(), boom)
+    for bad in (dict(kappa=-1.0), dict(strategy=7), dict(precision=3),
+                dict(reserved=1), dict(grid_mask=8)):
+        with pytest.raises(xs.XsError) as e:
+            xs.xs_tune_search(7, xs.xs_tune_config_default(**bad), Recorder())
+        assert e.value.status == xs.XS_EINVAL, bad
