@@ -161,7 +161,8 @@ def declared_functions() -> list:
     """Names of the functions include/xs.h declares."""
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(xs_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(
+        r"^(?:xs_status|const char\*)\s+(xs_[a-z_0-9]+)\s*\(", text, re.M)))
 
 
 def load_library(path: str = LIB_PATH):
