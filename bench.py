@@ -138,6 +138,10 @@ def main(argv=None):
                     help="skip the 5.7 GB unionized index table")
     ap.add_argument("--params", type=str, default=None,
                     help="JSON dict of FP32 params instead of tuning")
+    ap.add_argument("--tune-evals", type=int, default=48,
+                    help="evaluation budget of the forest-surrogate tuner")
+    ap.add_argument("--tune-strategy", choices=["forest", "exhaustive"],
+                    default="forest")
     ap.add_argument("--only", choices=["plain", "tuned"], default=None,
                     help="time one form only (for profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -173,7 +177,7 @@ def main(argv=None):
     nbar = synth.mean_nuclides(t, q)
     flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH
     if not args.no_union:
-        flags |= xs.XS_BUILD_UNIONIZED
+        flags |= xs.XS_BUILD_UNIONIZED | xs.XS_BUILD_UNION_BY_MATERIAL
     t0 = time.perf_counter()
     h = xs.xs_create_tables(t, flags, args.bins)
     build_s = time.perf_counter() - t0
@@ -221,17 +225,31 @@ def main(argv=None):
         plain = measure(p_plain, "plain_fp64")
         log(f"plain FP64: {plain['value']:.4g} lookups/s, "
             f"{plain['ms_per_step']:.3f} ms/step")
+    tune_report = None
     if args.only in (None, "tuned"):
         if args.params:
             p32 = xs.make_params(xs.XS_FP32, **json.loads(args.params))
         else:
-            p32 = xs.make_params(xs.XS_FP32, grid="hash",
-                                 sort="material_energy", block_size=256,
-                                 lookups_per_thread=2, lds_stage=0,
-                                 sort_threshold=20000,
-                                 queue=xs.XS_QUEUE_COMPACT)
+            cfg = xs.xs_tune_config_default(
+                precision=xs.XS_FP32,
+                strategy=(xs.XS_TUNE_FOREST if args.tune_strategy == "forest"
+                          else xs.XS_TUNE_EXHAUSTIVE),
+                max_evals=args.tune_evals, reps=3, warmup=1)
+            log(f"tuning the FP32 form ({args.tune_strategy}, "
+                f"{args.tune_evals} evaluations)")
+            t0 = time.perf_counter()
+            r = xs.xs_tune(h, E, m, cfg)
+            tune_report = r.as_dict()
+            tune_report["tune_s"] = time.perf_counter() - t0
+            log(f"tuned in {tune_report['tune_s']:.1f} s: best {r.best_ms:.3f} "
+                f"ms at evaluation {r.best_eval}/{r.evaluated}, baseline "
+                f"{r.baseline_ms:.3f} ms, {r.cut} cut")
+            # the tuned entry is recorded in the handle: resolve it as a
+            # caller passing automatic parameters would
+            p32 = xs.xs_resolve_params(h, n, xs.xs_params_default(xs.XS_FP32))
         log("timing FP32 form with", p32.as_dict())
         tuned = measure(p32, "tuned_fp32")
+        tuned["tuner"] = tune_report
         log(f"FP32 tuned: {tuned['value']:.4g} lookups/s, "
             f"{tuned['ms_per_step']:.3f} ms/step")
 

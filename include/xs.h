@@ -89,6 +89,11 @@ typedef int32_t xs_status;
 #define XS_BUILD_FP32 1u
 #define XS_BUILD_HASH 2u
 #define XS_BUILD_UNIONIZED 4u
+/* With XS_BUILD_UNIONIZED: store the union index per material, a block
+ * [U][L_m] of the brackets of material m's list, instead of [U][K].  A lookup
+ * then reads L_m contiguous indices instead of a K-wide row; memory is
+ * U * sum(L_m) * 4 bytes instead of U * K * 4. */
+#define XS_BUILD_UNION_BY_MATERIAL 8u
 
 typedef struct xs_tables_s* xs_tables_t;
 
@@ -314,6 +319,57 @@ xs_status xs_tune(xs_tables_t tables, int64_t n, const double* d_E,
 /* Records complete parameters (no XS_AUTO field) as tuned for the class of
  * n, e.g. restored from a cache file; p == NULL clears every tuned entry. */
 xs_status xs_set_tuned(xs_tables_t tables, int64_t n, const xs_params* p);
+
+/* ---- request streams ------------------------------------------------------ */
+
+/* Many uneven batches served by one persistent kernel launched from a HIP
+ * graph (paper section 5.1: the particle buffer is refilled after each
+ * kernel call, and with short kernels launches and queue-count transfers to
+ * the host leave bubbles).  Each block of the kernel claims 1024-lookup tiles
+ * of the batch with an atomic counter, sorts the tile in LDS by material and
+ * energy, looks it up, and stamps the request's first and last tile with the
+ * device wall clock.  Results equal xs_lookup_batch's bit for bit. */
+typedef struct xs_stream_s* xs_stream_t;
+
+typedef struct {
+  int64_t n;              /* lookups of the request, 0 <= n < 2^31 */
+  const double* d_E;      /* DEVICE [n] */
+  const int32_t* d_mat;   /* DEVICE [n] */
+  void* d_out;            /* DEVICE [n][5] of the stream's precision */
+} xs_request;
+
+typedef struct {
+  int64_t n;
+  double start_us;        /* first tile start, from the batch's first start */
+  double end_us;          /* last tile end, same origin */
+  double latency_us;      /* end_us - start_us (0 for an empty request) */
+} xs_request_stats;
+
+/* Creates a stream for batches of up to max_requests requests on `stream`
+ * (a hipStream_t as void*).  params (NULL: all automatic, FP64) fixes the
+ * precision, grid method and nuclides in flight; sort, block size, lookups
+ * per lane and threshold do not apply.  Captures the graph once. */
+xs_status xs_stream_create(xs_tables_t tables, const xs_params* params,
+                           int32_t max_requests, void* stream,
+                           xs_stream_t* out);
+
+/* Enqueues one batch (HOST array of count descriptors, read during the call)
+ * on the stream: descriptor upload, then one graph launch.  One batch may be
+ * in flight per stream object; XS_EINVAL if the previous one was not
+ * waited for. */
+xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
+                           int32_t count);
+
+/* Waits for the batch and fills stats[count] (may be NULL) and the batch's
+ * device makespan in microseconds (may be NULL). */
+xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
+                         double* makespan_us);
+
+/* The resolved parameters the stream runs with. */
+xs_status xs_stream_params(xs_stream_t s, xs_params* out);
+
+/* Waits for any batch in flight and frees the stream.  NULL is a no-op. */
+xs_status xs_stream_destroy(xs_stream_t s);
 
 /* ---- measurement --------------------------------------------------------- */
 

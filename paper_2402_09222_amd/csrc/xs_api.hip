@@ -90,8 +90,12 @@ xs_status validate_desc(const xs_table_desc* d) {
     return fail(XS_ETABLE, "n_materials must be in [1, 65536]");
   if (!d->mat_offsets || !d->mat_nuclides || !d->mat_density)
     return fail(XS_EINVAL, "material arrays must not be NULL");
-  if (d->build_flags & ~(XS_BUILD_FP32 | XS_BUILD_HASH | XS_BUILD_UNIONIZED))
+  if (d->build_flags & ~(XS_BUILD_FP32 | XS_BUILD_HASH | XS_BUILD_UNIONIZED |
+                         XS_BUILD_UNION_BY_MATERIAL))
     return fail(XS_EINVAL, "unknown build flag bits 0x%x", d->build_flags);
+  if ((d->build_flags & XS_BUILD_UNION_BY_MATERIAL) &&
+      !(d->build_flags & XS_BUILD_UNIONIZED))
+    return fail(XS_EINVAL, "XS_BUILD_UNION_BY_MATERIAL needs XS_BUILD_UNIONIZED");
   if ((d->build_flags & XS_BUILD_HASH) &&
       (d->n_hash_bins < 1 || d->n_hash_bins > 100000))
     return fail(XS_EINVAL, "n_hash_bins must be in [1, 100000]");
@@ -492,12 +496,16 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
     double* u_dev;
     if ((st = upload(h, u.data(), u.size(), &u_dev, s))) return cleanup(st);
     void* uidx;
-    const size_t bytes = (size_t)U * K * 4;
+    const bool by_mat = (desc->build_flags & XS_BUILD_UNION_BY_MATERIAL) != 0;
+    const size_t bytes = (size_t)U * (by_mat ? (size_t)L : (size_t)K) * 4;
     if ((st = alloc_dev(h, bytes, &uidx))) return cleanup(st);
     d.U = U;
     d.u = u_dev;
     d.uidx = (const int32_t*)uidx;
-    hipError_t e = launch_union_index(d, goff_dev, (int32_t*)uidx, s);
+    d.union_by_material = by_mat ? 1 : 0;
+    hipError_t e = by_mat
+        ? launch_union_index_by_material(d, L, (int32_t*)uidx, s)
+        : launch_union_index(d, goff_dev, (int32_t*)uidx, s);
     if (e != hipSuccess)
       return cleanup(fail(XS_EHIP, "union index launch failed: %s",
                           hipGetErrorString(e)));

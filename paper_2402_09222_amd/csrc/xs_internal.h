@@ -58,7 +58,9 @@ struct DevTables {
   // unionized grid
   int64_t U;                 // union points (0 = not built)
   const double* u;           // [U]
-  const int32_t* uidx;       // [U * K]: bracket of u[j] in nuclide k
+  const int32_t* uidx;       // [U][K], or per material m a block [U][L_m]
+                             // at U * moff[m] (union_by_material)
+  int32_t union_by_material;
 };
 
 // ---- sort key ------------------------------------------------------------
@@ -125,6 +127,8 @@ hipError_t launch_hash_build(const DevTables& t, const int32_t* goff_dev,
                              double dln, int32_t* H, hipStream_t s);
 hipError_t launch_union_index(const DevTables& t, const int32_t* goff_dev,
                               int32_t* uidx, hipStream_t s);
+hipError_t launch_union_index_by_material(const DevTables& t, int32_t Ltot,
+                                          int32_t* uidx, hipStream_t s);
 
 // Lookup kernels (xs_lookup_*.hip).  count_dev, when not null, holds the
 // number of valid entries of perm (device-side queue length).

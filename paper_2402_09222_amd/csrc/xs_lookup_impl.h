@@ -120,9 +120,9 @@ struct Locator;
 
 template <>
 struct Locator<XS_GRID_NUCLIDE> {
-  __device__ __forceinline__ void init(const DevTables&, double) {}
+  __device__ __forceinline__ void init(const DevTables&, double, int) {}
   __device__ __forceinline__ int start(const DevTables& t, const MatRec& r,
-                                       double e) const {
+                                       int, double e) const {
     return min(bisect_le(t.E + r.base, r.n, e), r.n - 2);
   }
   __device__ __forceinline__ const int32_t* next_row(const DevTables&) const {
@@ -133,12 +133,12 @@ struct Locator<XS_GRID_NUCLIDE> {
 template <>
 struct Locator<XS_GRID_HASH> {
   const int32_t* hrow;  // H[b]
-  __device__ __forceinline__ void init(const DevTables& t, double e) {
+  __device__ __forceinline__ void init(const DevTables& t, double e, int) {
     double x = (log(e) - t.ln_emin) * t.inv_dln;
     x = fmin(fmax(x, 0.0), (double)(t.B - 1));
     hrow = t.H + (int64_t)(int)x * t.K;
   }
-  __device__ __forceinline__ int start(const DevTables&, const MatRec& r,
+  __device__ __forceinline__ int start(const DevTables&, const MatRec& r, int,
                                        double) const {
     return hrow[r.k];
   }
@@ -147,59 +147,74 @@ struct Locator<XS_GRID_HASH> {
   }
 };
 
+// Row j of the index table: [U][K] (column = nuclide id) or, when built by
+// material, material m's block [U][L_m] (column = position in m's list).
 template <>
 struct Locator<XS_GRID_UNIONIZED> {
-  const int32_t* urow;  // uidx[j]
-  __device__ __forceinline__ void init(const DevTables& t, double e) {
-    urow = t.uidx + (int64_t)bisect_le(t.u, (int)t.U, e) * t.K;
+  const int32_t* urow;
+  int jbase;  // first list position of the material (by-material layout)
+  __device__ __forceinline__ void init(const DevTables& t, double e, int m) {
+    const int64_t j = bisect_le(t.u, (int)t.U, e);
+    if (t.union_by_material) {
+      jbase = t.moff[m];
+      const int64_t L = t.moff[m + 1] - jbase;
+      urow = t.uidx + t.U * jbase + j * L;
+    } else {
+      jbase = 0;
+      urow = t.uidx + j * t.K;
+    }
   }
-  __device__ __forceinline__ int start(const DevTables&, const MatRec& r,
-                                       double) const {
-    return urow[r.k];
+  __device__ __forceinline__ int start(const DevTables& t, const MatRec& r,
+                                       int jg, double) const {
+    return urow[t.union_by_material ? jg - jbase : r.k];
   }
   __device__ __forceinline__ const int32_t* next_row(const DevTables&) const {
     return nullptr;
   }
 };
 
+// Field-wise out = c ? a : b.  Selecting whole records by reference would
+// make the compiler select an address and keep the records on the stack.
+template <class R>
+__device__ __forceinline__ void select_rec(bool c, const R& a, const R& b,
+                                           R& out) {
+#pragma unroll
+  for (int k = 0; k < XS_CHANNELS; ++k) out.x[k] = c ? a.x[k] : b.x[k];
+  out.e = c ? a.e : b.e;
+}
+
 // Records around a candidate index: three for the hash grid (candidate and
 // the next two), two (the bracket) otherwise.
 template <int GRID, int PREC>
 struct Window {
   using R = typename RecOf<PREC>::T;
-  static constexpr int kN = GRID == XS_GRID_HASH ? 3 : 2;
-  R r[kN];
+  static constexpr bool kHash = GRID == XS_GRID_HASH;
+  R r0, r1, r2;
   __device__ __forceinline__ void load(const DevTables& t, const MatRec& m,
                                        int i) {
     const R* p = RecOf<PREC>::base(t) + m.base;
-    r[0] = p[i];
-    r[1] = p[i + 1];
-    if (kN == 3) r[kN - 1] = p[min(i + 2, m.n - 1)];
+    r0 = p[i];
+    r1 = p[i + 1];
+    if (kHash) r2 = p[min(i + 2, m.n - 1)];
   }
   // Final bracket pair into lo/hi.
   __device__ __forceinline__ void finish(const DevTables& t, const MatRec& m,
                                          const Locator<GRID>& loc, int cand,
                                          double e, R& lo, R& hi) const {
-    if (GRID != XS_GRID_HASH) {
-      lo = r[0];
-      hi = r[1];
+    if (!kHash) {
+      lo = r0;
+      hi = r1;
       return;
     }
-    int i;
-    if (cand + 1 <= m.n - 2 && r[1].e <= e) {
-      i = cand + 1;
-      lo = r[1];
-      hi = r[kN - 1];
-    } else {
-      i = cand;
-      lo = r[0];
-      hi = r[1];
-    }
+    const bool up = cand + 1 <= m.n - 2 && r1.e <= e;
+    const int i = up ? cand + 1 : cand;
+    select_rec(up, r1, r0, lo);
+    select_rec(up, r2, r1, hi);
     if (!bracket_ok(i, m.n, e, lo, hi)) {
-      i = hash_slow(t, m, loc.next_row(t), cand, e);
+      const int j = hash_slow(t, m, loc.next_row(t), cand, e);
       const R* p = RecOf<PREC>::base(t) + m.base;
-      lo = p[i];
-      hi = p[i + 1];
+      lo = p[j];
+      hi = p[j + 1];
     }
   }
 };
@@ -315,7 +330,7 @@ struct Acc<XS_FP32> {
 // issue one index load each.
 template <int GRID, int LPT, int U>
 __device__ __forceinline__ void candidates(const DevTables& t,
-                                           const MatRec (&r)[U],
+                                           const MatRec (&r)[U], int j,
                                            const double (&e)[LPT],
                                            const Locator<GRID> (&loc)[LPT],
                                            int (&cand)[LPT][U]) {
@@ -353,7 +368,7 @@ __device__ __forceinline__ void candidates(const DevTables& t,
 #pragma unroll
   for (int l = 0; l < LPT; ++l)
 #pragma unroll
-    for (int u = 0; u < U; ++u) cand[l][u] = loc[l].start(t, r[u], e[l]);
+    for (int u = 0; u < U; ++u) cand[l][u] = loc[l].start(t, r[u], j + u, e[l]);
 }
 
 template <int GRID, int PREC, int LPT, int U>
@@ -371,7 +386,7 @@ __device__ __forceinline__ void walk_material(const DevTables& t, int mat,
 #pragma unroll
       for (int u = 0; u < U; ++u) r[u] = ld_const(t.mrec + j + u);
       int cand[LPT][U];
-      candidates<GRID, LPT, U>(t, r, e, loc, cand);
+      candidates<GRID, LPT, U>(t, r, j, e, loc, cand);
       W w[LPT][U];
 #pragma unroll
       for (int l = 0; l < LPT; ++l)
@@ -392,7 +407,7 @@ __device__ __forceinline__ void walk_material(const DevTables& t, int mat,
   for (; j < j1; ++j) {
     const MatRec r[1] = {ld_const(t.mrec + j)};
     int cand[LPT][1];
-    candidates<GRID, LPT, 1>(t, r, e, loc, cand);
+    candidates<GRID, LPT, 1>(t, r, j, e, loc, cand);
     W w[LPT];
 #pragma unroll
     for (int l = 0; l < LPT; ++l) w[l].load(t, r[0], cand[l][0]);
@@ -458,7 +473,7 @@ __global__ __launch_bounds__(max_block_for(LPT, U)) void k_lookup(
     Acc<PREC> acc[LPT];
 #pragma unroll
     for (int l = 0; l < LPT; ++l) {
-      loc[l].init(t, e[l]);
+      loc[l].init(t, e[l], m[0]);
       acc[l].zero();
     }
     if (wave_uniform)
@@ -476,7 +491,7 @@ __global__ __launch_bounds__(max_block_for(LPT, U)) void k_lookup(
     const double e1[1] = {e[l]};
     Locator<GRID> loc[1];
     Acc<PREC> acc[1];
-    loc[0].init(t, e[l]);
+    loc[0].init(t, e[l], m[l]);
     acc[0].zero();
     walk_material<GRID, PREC, 1, U>(t, m[l], e1, loc, acc);
     acc[0].store(a.out, o[l]);
@@ -510,10 +525,10 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
     return;
   }
   Locator<GRID> loc;
-  loc.init(t, e);
+  loc.init(t, e, m);
   for (int j = j0; j < j1; ++j) {
     const MatRec r = t.mrec[j];
-    const int cand = loc.start(t, r, e);
+    const int cand = loc.start(t, r, j, e);
     int i = cand;
     if (GRID == XS_GRID_HASH) {
       const double* g = t.E + r.base;

@@ -1,0 +1,425 @@
+// Request streams: many uneven lookup batches served by one persistent,
+// graph-launched kernel (xs_stream_*).
+//
+// The paper's particle buffer is refilled after every kernel call and the
+// host launches one event kernel per queue (section 5.1, "maximum number of
+// particles in-flight" and "queuing logic"); with short kernels the launch
+// and the count transfer to the host leave bubbles.  Here a batch of requests
+// is described once in device memory and a single launch drains it: each
+// block claims the next tile of 1024 lookups with an atomic counter, sorts
+// the tile in LDS by (material, energy) so that waves hold one material,
+// runs the lookup walk of the main kernel and stamps the request's first and
+// last tile times with the device wall clock.  Every block leaves its loop
+// once the counter passes the batch's tile count, so the grid always drains.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "xs_lookup_impl.h"
+
+namespace xs {
+namespace {
+
+constexpr int kStreamThreads = 256;
+constexpr int kStreamTile = 1024;  // lookups per claimed tile
+constexpr int kPerLane = kStreamTile / kStreamThreads;
+
+struct ReqDev {
+  const double* E;
+  const int32_t* mat;
+  void* out;
+  int64_t n;
+  int64_t tile_begin;  // first global tile of the request
+};
+
+struct StreamHeader {
+  int32_t count;       // requests in the batch
+  int32_t pad;
+  int64_t tiles;       // tiles in the batch
+};
+
+struct StreamState {
+  unsigned long long counter;  // next tile to claim
+  unsigned long long t_min;    // earliest tile start of the batch
+};
+
+// Tile sort key: material in the high 16 bits, then the top 16 bits of the
+// energy key; lanes without a lookup sort last.
+__device__ __forceinline__ uint32_t tile_key(double e, int m, int M,
+                                             int64_t ebits_min, int eshift) {
+  int64_t d = __double_as_longlong(e) - ebits_min;
+  d = d < 0 ? 0 : (d >> eshift);
+  const uint32_t ek = (uint32_t)(d > 0xffff ? 0xffff : d);
+  const uint32_t mm = (uint32_t)(m < 0 ? 0 : (m >= M ? M - 1 : m));
+  return (mm << 16) | ek;
+}
+
+// Init node of the graph: resets the claim counter and the stamps.
+__global__ void k_stream_init(StreamState* st, unsigned long long* t_first,
+                              unsigned long long* t_last, int max_requests) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    st->counter = 0;
+    st->t_min = ~0ull;
+  }
+  if (i < max_requests) {
+    t_first[i] = ~0ull;
+    t_last[i] = 0;
+  }
+}
+
+template <int GRID, int PREC, int U>
+__global__ __launch_bounds__(kStreamThreads) void k_stream(
+    const DevTables t, const StreamHeader* __restrict__ hdr,
+    const ReqDev* __restrict__ reqs, StreamState* st,
+    unsigned long long* t_first, unsigned long long* t_last,
+    int64_t ebits_min, int eshift) {
+  __shared__ uint32_t skey[kStreamTile];
+  __shared__ uint16_t sidx[kStreamTile];
+  __shared__ unsigned long long claim;
+  const int tid = threadIdx.x;
+  const int count = hdr->count;
+  const int64_t tiles = hdr->tiles;
+
+  for (;;) {
+    if (tid == 0) claim = atomicAdd(&st->counter, 1ull);
+    __syncthreads();
+    const int64_t g = (int64_t)claim;
+    __syncthreads();
+    if (g >= tiles) break;  // every block reaches this once the batch is done
+    const unsigned long long t0 = wall_clock64();
+
+    // Request holding tile g (largest r with tile_begin <= g).
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (reqs[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    const ReqDev R = reqs[lo];
+    const int64_t base = (g - R.tile_begin) * kStreamTile;
+
+    // Load and key the tile, then sort it in LDS (bitonic network).
+#pragma unroll
+    for (int p = 0; p < kPerLane; ++p) {
+      const int pos = tid + p * kStreamThreads;
+      const int64_t q = base + pos;
+      uint32_t key = 0xffffffffu;
+      if (q < R.n) key = tile_key(R.E[q], R.mat[q], t.M, ebits_min, eshift);
+      skey[pos] = key;
+      sidx[pos] = (uint16_t)pos;
+    }
+    __syncthreads();
+    for (int k = 2; k <= kStreamTile; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+        for (int p = 0; p < kPerLane / 2; ++p) {
+          // pair (a, a ^ j) with a's bit j clear
+          const int i = tid + p * kStreamThreads;
+          const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+          const int b = a | j;
+          const bool up = (a & k) == 0;
+          const uint32_t ka = skey[a], kb = skey[b];
+          if ((ka > kb) == up) {
+            skey[a] = kb;
+            skey[b] = ka;
+            const uint16_t t2 = sidx[a];
+            sidx[a] = sidx[b];
+            sidx[b] = t2;
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // Look up in sorted order: lane tid takes sorted positions tid, tid+256..
+#pragma unroll 1
+    for (int p = 0; p < kPerLane; ++p) {
+      const int pos = tid + p * kStreamThreads;
+      const int64_t q = base + sidx[pos];
+      const bool act = q < R.n;
+      double e = 1.0;
+      int m = -1;
+      if (act) {
+        e = R.E[q];
+        m = R.mat[q];
+      }
+      const bool ok = act && valid_query(e, m, t.M);
+      if (act && !ok) Acc<PREC>::store_nan(R.out, q);
+      const int mu = __builtin_amdgcn_readfirstlane(m);
+      const bool wave_uniform = __all(ok && m == mu);
+      if (ok || wave_uniform) {
+        const double e1[1] = {e};
+        Locator<GRID> loc[1];
+        Acc<PREC> acc[1];
+        loc[0].init(t, e, m);
+        acc[0].zero();
+        if (wave_uniform)
+          walk_material<GRID, PREC, 1, U>(t, mu, e1, loc, acc);
+        else
+          walk_material<GRID, PREC, 1, U>(t, m, e1, loc, acc);
+        acc[0].store(R.out, q);
+      }
+    }
+    __syncthreads();  // the tile's LDS is reused by the next claim
+    if (tid == 0) {
+      const unsigned long long t1 = wall_clock64();
+      atomicMin(&t_first[lo], t0);
+      atomicMax(&t_last[lo], t1);
+      atomicMin(&st->t_min, t0);
+    }
+  }
+}
+
+}  // namespace
+}  // namespace xs
+
+struct xs_stream_s {
+  xs_tables_t tables = nullptr;
+  xs_params params{};
+  hipStream_t user = nullptr;
+  hipStream_t capture = nullptr;
+  int32_t max_requests = 0;
+  int32_t pending = 0;  // requests of the batch in flight (0 = idle)
+  xs::StreamHeader* hdr_dev = nullptr;
+  xs::ReqDev* reqs_dev = nullptr;
+  xs::StreamState* state_dev = nullptr;
+  unsigned long long* t_first_dev = nullptr;
+  unsigned long long* t_last_dev = nullptr;
+  void* host = nullptr;  // pinned: header + descriptors
+  int64_t n_req[1] = {0};
+  std::vector<int64_t> sizes;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  int blocks = 0;
+  double clock_khz = 0;
+};
+
+namespace xs {
+namespace {
+
+void stream_release(xs_stream_s* s) {
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->done) (void)hipEventDestroy(s->done);
+  if (s->capture) (void)hipStreamDestroy(s->capture);
+  for (void* p : {(void*)s->hdr_dev, (void*)s->reqs_dev, (void*)s->state_dev,
+                  (void*)s->t_first_dev, (void*)s->t_last_dev})
+    if (p) (void)hipFree(p);
+  if (s->host) (void)hipHostFree(s->host);
+  delete s;
+}
+
+template <int GRID, int PREC, int U>
+hipError_t launch_stream_kernel(xs_stream_s* s, hipStream_t st) {
+  const DevTables& t = s->tables->d;
+  const int64_t ebits_min = [&] {
+    int64_t b;
+    std::memcpy(&b, &s->tables->info.e_min, 8);
+    return b;
+  }();
+  int64_t span;
+  {
+    int64_t bmax;
+    std::memcpy(&bmax, &s->tables->info.e_max, 8);
+    span = bmax - ebits_min;
+  }
+  int shift = 0;
+  while ((span >> shift) > 0xffff) ++shift;
+  hipLaunchKernelGGL((k_stream<GRID, PREC, U>), dim3(s->blocks),
+                     dim3(kStreamThreads), 0, st, t, s->hdr_dev, s->reqs_dev,
+                     s->state_dev, s->t_first_dev, s->t_last_dev, ebits_min,
+                     shift);
+  return hipGetLastError();
+}
+
+template <int GRID, int PREC>
+hipError_t launch_stream_u(xs_stream_s* s, hipStream_t st) {
+  switch (s->params.unroll) {
+    case 1: return launch_stream_kernel<GRID, PREC, 1>(s, st);
+    case 2: return launch_stream_kernel<GRID, PREC, 2>(s, st);
+    default: return launch_stream_kernel<GRID, PREC, 4>(s, st);
+  }
+}
+
+template <int GRID>
+hipError_t launch_stream_p(xs_stream_s* s, hipStream_t st) {
+  return s->params.precision == XS_FP64 ? launch_stream_u<GRID, XS_FP64>(s, st)
+                                        : launch_stream_u<GRID, XS_FP32>(s, st);
+}
+
+hipError_t launch_stream(xs_stream_s* s, hipStream_t st) {
+  switch (s->params.grid) {
+    case XS_GRID_NUCLIDE: return launch_stream_p<XS_GRID_NUCLIDE>(s, st);
+    case XS_GRID_HASH: return launch_stream_p<XS_GRID_HASH>(s, st);
+    default: return launch_stream_p<XS_GRID_UNIONIZED>(s, st);
+  }
+}
+
+}  // namespace
+}  // namespace xs
+
+using namespace xs;
+
+extern "C" {
+
+xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
+                           int32_t max_requests, void* stream,
+                           xs_stream_t* out) {
+  clear_error();
+  if (!h || !out) return fail(XS_EINVAL, "tables and out must not be NULL");
+  if (max_requests < 1 || max_requests > (1 << 20))
+    return fail(XS_EINVAL, "max_requests must be in [1, 2^20]");
+  xs_params p;
+  // Resolved like a large batch; sort, block size, lookups per lane and the
+  // threshold do not apply (tiles are sorted in LDS, blocks are 256 lanes).
+  if (xs_status st = xs_resolve_params(h, 1 << 20, params, &p)) return st;
+  auto* s = new (std::nothrow) xs_stream_s();
+  if (!s) return fail(XS_ENOMEM, "host allocation failed");
+  s->tables = h;
+  s->params = p;
+  s->user = (hipStream_t)stream;
+  s->max_requests = max_requests;
+  auto bail = [&](xs_status st) {
+    stream_release(s);
+    return st;
+  };
+  auto hip = [&](hipError_t e, const char* what) -> xs_status {
+    if (e == hipSuccess) return XS_OK;
+    return fail(e == hipErrorOutOfMemory ? XS_ENOMEM : XS_EHIP, "%s: %s", what,
+                hipGetErrorString(e));
+  };
+  xs_status st;
+  const size_t req_bytes = sizeof(ReqDev) * (size_t)max_requests;
+  if ((st = hip(hipMalloc(&s->hdr_dev, sizeof(StreamHeader)), "hipMalloc")) ||
+      (st = hip(hipMalloc(&s->reqs_dev, req_bytes), "hipMalloc")) ||
+      (st = hip(hipMalloc(&s->state_dev, sizeof(StreamState)), "hipMalloc")) ||
+      (st = hip(hipMalloc(&s->t_first_dev, 8 * (size_t)max_requests), "hipMalloc")) ||
+      (st = hip(hipMalloc(&s->t_last_dev, 8 * (size_t)max_requests), "hipMalloc")) ||
+      (st = hip(hipHostMalloc(&s->host, sizeof(StreamHeader) + req_bytes),
+                "hipHostMalloc")) ||
+      (st = hip(hipEventCreateWithFlags(&s->done, hipEventDisableTiming),
+                "hipEventCreate")) ||
+      (st = hip(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking),
+                "hipStreamCreate")))
+    return bail(st);
+  int dev = 0, cus = 0, khz = 0;
+  if ((st = hip(hipGetDevice(&dev), "hipGetDevice")) ||
+      (st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                      dev), "hipDeviceGetAttribute")) ||
+      (st = hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev),
+                "hipDeviceGetAttribute")))
+    return bail(st);
+  s->blocks = std::max(1, cus) * 8;
+  s->clock_khz = khz > 0 ? khz : 100000.0;
+
+  // Capture [init, persistent kernel] once; every submit replays it.
+  if ((st = hip(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal),
+                "hipStreamBeginCapture")))
+    return bail(st);
+  hipLaunchKernelGGL(k_stream_init, dim3((max_requests + 255) / 256), dim3(256),
+                     0, s->capture, s->state_dev, s->t_first_dev,
+                     s->t_last_dev, max_requests);
+  hipError_t le = hipGetLastError();
+  if (le == hipSuccess) le = launch_stream(s, s->capture);
+  hipError_t ce = hipStreamEndCapture(s->capture, &s->graph);
+  if ((st = hip(le, "stream kernel launch")) || (st = hip(ce, "hipStreamEndCapture")))
+    return bail(st);
+  if ((st = hip(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0),
+                "hipGraphInstantiate")))
+    return bail(st);
+  *out = s;
+  return XS_OK;
+}
+
+xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
+                           int32_t count) {
+  clear_error();
+  if (!s) return fail(XS_EINVAL, "stream is NULL");
+  if (s->pending) return fail(XS_EINVAL, "a batch is still in flight; call "
+                              "xs_stream_wait first");
+  if (count < 1 || count > s->max_requests)
+    return fail(XS_EINVAL, "count must be in [1, %d]", s->max_requests);
+  if (!reqs) return fail(XS_EINVAL, "reqs is NULL");
+  auto* hdr = (StreamHeader*)s->host;
+  auto* rd = (ReqDev*)(hdr + 1);
+  int64_t tiles = 0;
+  s->sizes.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    const xs_request& r = reqs[i];
+    if (r.n < 0 || r.n > 0x7fffffffLL)
+      return fail(XS_EINVAL, "request %d: n out of range", i);
+    if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
+      return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
+    rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles};
+    tiles += (r.n + kStreamTile - 1) / kStreamTile;
+    s->sizes[i] = r.n;
+  }
+  hdr->count = count;
+  hdr->pad = 0;
+  hdr->tiles = tiles;
+  XS_HIP(hipMemcpyAsync(s->hdr_dev, hdr, sizeof(StreamHeader),
+                        hipMemcpyHostToDevice, s->user));
+  XS_HIP(hipMemcpyAsync(s->reqs_dev, rd, sizeof(ReqDev) * count,
+                        hipMemcpyHostToDevice, s->user));
+  XS_HIP(hipGraphLaunch(s->exec, s->user));
+  XS_HIP(hipEventRecord(s->done, s->user));
+  s->pending = count;
+  return XS_OK;
+}
+
+xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
+                         double* makespan_us) {
+  clear_error();
+  if (!s) return fail(XS_EINVAL, "stream is NULL");
+  if (!s->pending) return fail(XS_EINVAL, "no batch in flight");
+  XS_HIP(hipEventSynchronize(s->done));
+  const int count = s->pending;
+  s->pending = 0;
+  std::vector<unsigned long long> a(count), b(count);
+  StreamState state;
+  XS_HIP(hipMemcpy(a.data(), s->t_first_dev, 8 * (size_t)count,
+                   hipMemcpyDeviceToHost));
+  XS_HIP(hipMemcpy(b.data(), s->t_last_dev, 8 * (size_t)count,
+                   hipMemcpyDeviceToHost));
+  XS_HIP(hipMemcpy(&state, s->state_dev, sizeof(state), hipMemcpyDeviceToHost));
+  const double us_per_tick = 1000.0 / s->clock_khz;
+  unsigned long long tmax = 0;
+  for (int i = 0; i < count; ++i) tmax = std::max(tmax, b[i]);
+  if (makespan_us)
+    *makespan_us = state.t_min == ~0ull ? 0.0 : (tmax - state.t_min) * us_per_tick;
+  if (stats) {
+    for (int i = 0; i < count; ++i) {
+      xs_request_stats& r = stats[i];
+      r.n = s->sizes[i];
+      if (a[i] == ~0ull) {
+        r.start_us = r.end_us = r.latency_us = 0.0;
+        continue;
+      }
+      r.start_us = (a[i] - state.t_min) * us_per_tick;
+      r.end_us = (b[i] - state.t_min) * us_per_tick;
+      r.latency_us = r.end_us - r.start_us;
+    }
+  }
+  return XS_OK;
+}
+
+xs_status xs_stream_params(xs_stream_t s, xs_params* out) {
+  clear_error();
+  if (!s || !out) return fail(XS_EINVAL, "stream and out must not be NULL");
+  *out = s->params;
+  return XS_OK;
+}
+
+xs_status xs_stream_destroy(xs_stream_t s) {
+  clear_error();
+  if (!s) return XS_OK;
+  if (s->pending) (void)hipEventSynchronize(s->done);
+  stream_release(s);
+  return XS_OK;
+}
+
+}  // extern "C"

@@ -25,6 +25,7 @@ XS_SORT_NONE, XS_SORT_MATERIAL, XS_SORT_ENERGY, XS_SORT_MATERIAL_ENERGY = 0, 1, 
 XS_SORT_BAND_MATERIAL = 4
 XS_QUEUE_COMPACT, XS_QUEUE_PREDICATED = 0, 1
 XS_BUILD_FP32, XS_BUILD_HASH, XS_BUILD_UNIONIZED = 1, 2, 4
+XS_BUILD_UNION_BY_MATERIAL = 8
 INT64_MAX = (1 << 63) - 1
 
 GRIDS = {"nuclide": XS_GRID_NUCLIDE, "hash": XS_GRID_HASH,
@@ -149,6 +150,24 @@ class xs_tune_result(ctypes.Structure):
                 "best_eval": self.best_eval}
 
 
+class xs_request(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("d_E", ctypes.c_void_p),
+        ("d_mat", ctypes.c_void_p),
+        ("d_out", ctypes.c_void_p),
+    ]
+
+
+class xs_request_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("start_us", ctypes.c_double),
+        ("end_us", ctypes.c_double),
+        ("latency_us", ctypes.c_double),
+    ]
+
+
 XS_TUNE_EXHAUSTIVE, XS_TUNE_FOREST = 0, 1
 EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(xs_params),
                            ctypes.c_double, ctypes.POINTER(ctypes.c_double),
@@ -174,6 +193,12 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError(
             f"{path} is missing: build it with __graft_entry__.build() or "
             "python paper_2402_09222_amd/build.py")
+    try:
+        # torch bundles a HIP runtime; loading it first makes libxs.so bind to
+        # that same runtime instead of a second copy.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
     P = ctypes.POINTER
@@ -196,6 +221,11 @@ def load_library(path: str = LIB_PATH):
         "xs_tune": ([vp, i64, vp, vp, vp, vp, sz, vp, P(xs_tune_config),
                      P(xs_tune_result)], i32),
         "xs_set_tuned": ([vp, i64, P(xs_params)], i32),
+        "xs_stream_create": ([vp, P(xs_params), i32, vp, P(vp)], i32),
+        "xs_stream_submit": ([vp, P(xs_request), i32], i32),
+        "xs_stream_wait": ([vp, P(xs_request_stats), P(ctypes.c_double)], i32),
+        "xs_stream_params": ([vp, P(xs_params)], i32),
+        "xs_stream_destroy": ([vp], i32),
         "xs_status_string": ([i32], ctypes.c_char_p),
         "xs_last_error": ([], ctypes.c_char_p),
     }
@@ -506,3 +536,76 @@ def xs_set_tuned(tables: Tables, n: int, params: xs_params = None):
     _check(load_library().xs_set_tuned(
         tables.handle, n, ctypes.byref(params) if params is not None else None),
         "xs_set_tuned")
+
+
+class Stream:
+    """Owns an xs_stream_t (persistent-kernel request stream)."""
+
+    def __init__(self, handle: ctypes.c_void_p, max_requests: int):
+        self.handle = handle
+        self.max_requests = max_requests
+        self._keep = None
+        self._count = 0
+
+    def close(self):
+        if self.handle and self.handle.value:
+            _check(load_library().xs_stream_destroy(self.handle),
+                   "xs_stream_destroy")
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def xs_stream_create(tables: Tables, params: xs_params = None,
+                     max_requests: int = 4096, stream=None) -> Stream:
+    import torch
+    h = ctypes.c_void_p()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(load_library().xs_stream_create(
+        tables.handle, ctypes.byref(params) if params is not None else None,
+        max_requests, ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)),
+        "xs_stream_create")
+    return Stream(h, max_requests)
+
+
+def xs_stream_submit(stream: Stream, requests):
+    """requests: list of (E, mat, out) device tensors (out [n, 5] of the
+    stream's precision)."""
+    arr = (xs_request * len(requests))()
+    for i, (E, mat, out) in enumerate(requests):
+        _check_queries(E, mat)
+        if out.shape[0] < E.numel() or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [n, 5] tensor")
+        arr[i] = xs_request(E.numel(), E.data_ptr(), mat.data_ptr(),
+                            out.data_ptr())
+    stream._keep = list(requests)
+    stream._count = len(requests)
+    _check(load_library().xs_stream_submit(stream.handle, arr, len(requests)),
+           "xs_stream_submit")
+
+
+def xs_stream_wait(stream: Stream):
+    """Returns (stats list of dicts, makespan_us)."""
+    stats = (xs_request_stats * max(stream._count, 1))()
+    mk = ctypes.c_double()
+    _check(load_library().xs_stream_wait(stream.handle, stats, ctypes.byref(mk)),
+           "xs_stream_wait")
+    out = [dict(n=s.n, start_us=s.start_us, end_us=s.end_us,
+                latency_us=s.latency_us) for s in stats[:stream._count]]
+    stream._keep = None
+    return out, mk.value
+
+
+def xs_stream_params(stream: Stream) -> xs_params:
+    p = xs_params()
+    _check(load_library().xs_stream_params(stream.handle, ctypes.byref(p)),
+           "xs_stream_params")
+    return p
+
+
+def xs_stream_destroy(stream: Stream):
+    stream.close()

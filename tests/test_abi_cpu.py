@@ -135,7 +135,8 @@ def test_create_rejects_structure(lib):
     assert _create_status(t, n_channels=4)[0] == xs.XS_ETABLE
     assert _create_status(t, n_nuclides=0)[0] == xs.XS_ETABLE
     assert _create_status(t, n_materials=0)[0] == xs.XS_ETABLE
-    assert _create_status(t, flags=8)[0] == xs.XS_EINVAL
+    assert _create_status(t, flags=16)[0] == xs.XS_EINVAL
+    assert _create_status(t, flags=xs.XS_BUILD_UNION_BY_MATERIAL)[0] == xs.XS_EINVAL
     assert _create_status(t, flags=xs.XS_BUILD_HASH, bins=0)[0] == xs.XS_EINVAL
     assert _create_status(t, flags=xs.XS_BUILD_HASH, bins=100001)[0] == xs.XS_EINVAL
     # a nuclide with a single grid point

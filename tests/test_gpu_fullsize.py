@@ -104,6 +104,30 @@ def test_fp32_samples_and_bound(full, grid):
         assert np.array_equal(o2, o), k
 
 
+def test_union_by_material_full(full):
+    """Material-major union index (12.6 GB here): identical bits."""
+    if "out64" not in full:
+        pytest.skip("plain run failed")
+    say("union by material, full size")
+    h = xs.xs_create_tables(full["t"], xs.XS_BUILD_FP32 | xs.XS_BUILD_UNIONIZED |
+                            xs.XS_BUILD_UNION_BY_MATERIAL, 0)
+    try:
+        for k in (dict(sort="band_material", sort_threshold=0, lookups_per_thread=1,
+                       unroll=4),
+                  dict(sort="none", lookups_per_thread=2, unroll=1)):
+            p = xs.make_params(xs.XS_FP64, grid="unionized", block_size=256, **k)
+            out = xs.xs_lookup_batch(h, full["E"], full["m"], params=p)
+            torch.cuda.synchronize()
+            assert torch.equal(out.cpu(), full["out64"]), k
+        p = xs.make_params(xs.XS_FP32, grid="unionized", sort="band_material",
+                           sort_threshold=0, block_size=256, lookups_per_thread=1,
+                           unroll=2)
+        o = xs.xs_lookup_batch(h, full["E"], full["m"], params=p).cpu().numpy()
+        assert np.array_equal(o[full["pick"]], full["ref32"])
+    finally:
+        h.close()
+
+
 def test_ragged_batch(full):
     n = N - 9
     say("ragged", n)

@@ -262,6 +262,26 @@ def test_errors_from_device_calls(cfg1):
     small.close()
 
 
+def test_union_by_material(cfg1):
+    """The by-material union index gives the same brackets and bits."""
+    t, q = cfg1["t"], cfg1["q"]
+    h = xs.xs_create_tables(t, ALL_FLAGS | xs.XS_BUILD_UNION_BY_MATERIAL, 4000)
+    info = xs.xs_table_info(h)
+    assert info["bytes_union"] == info["union_size"] * (8 + 4 * len(t.mat_nuclides))
+    _, idx_ref, off = oracle.lookup(t, q.E, q.mat, with_index=True)
+    idx = xs.xs_lookup_indices(h, cfg1["E"], cfg1["m"], dev(off, torch.int64),
+                               grid="unionized")
+    torch.cuda.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), idx_ref)
+    for k in KNOBS:
+        out = run(h, cfg1["E"], cfg1["m"], grid="unionized", **k)
+        assert np.array_equal(out, cfg1["ref"]), k
+        out = run(h, cfg1["E"], cfg1["m"], precision=xs.XS_FP32,
+                  grid="unionized", **k)
+        assert np.array_equal(out, cfg1["ref32"]), k
+    h.close()
+
+
 def test_table_info(cfg1):
     info = xs.xs_table_info(cfg1["h"])
     t = cfg1["t"]
