@@ -209,7 +209,7 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.sort_threshold < 0) p.sort_threshold = t.sort_threshold;
   if (p.queue == XS_AUTO) p.queue = t.queue;
   if (p.unroll == 0 || p.unroll == XS_AUTO)
-    p.unroll = p.lookups_per_thread <= 2 ? t.unroll : 1;
+    p.unroll = (p.lookups_per_thread <= 2 && p.lds_stage != 1) ? t.unroll : 1;
 
   if (p.grid < 0 || p.grid > 2) return fail(XS_EINVAL, "unknown grid %d", p.grid);
   if (p.grid == XS_GRID_HASH && h->d.B == 0)
@@ -224,8 +224,9 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
                 p.lookups_per_thread);
   if (p.lds_stage != 0 && p.lds_stage != 1)
     return fail(XS_EINVAL, "lds_stage must be 0 or 1");
-  if (p.lds_stage == 1)
-    return fail(XS_EINVAL, "lds_stage = 1 is not available in this build");
+  if (p.lds_stage == 1 && (p.lookups_per_thread != 1 || p.unroll != 1))
+    return fail(XS_EINVAL, "lds_stage = 1 runs one lookup per lane with one "
+                "nuclide in flight (lookups_per_thread = unroll = 1)");
   if (p.queue != XS_QUEUE_COMPACT && p.queue != XS_QUEUE_PREDICATED)
     return fail(XS_EINVAL, "unknown queue mode %d", p.queue);
   if (p.unroll != 1 && p.unroll != 2 && p.unroll != 4)

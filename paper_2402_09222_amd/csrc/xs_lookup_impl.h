@@ -498,14 +498,30 @@ __global__ __launch_bounds__(max_block_for(LPT, U)) void k_lookup(
   }
 }
 
-// ---- validation path: brackets of every (lookup, nuclide) ---------------------
+// ---- exact bracket from the search grid -----------------------------------------
 //
-// Uses the same candidate and window logic as the lookup, reading energies
-// from the search grid instead of the records.
+// The same candidate and window logic as the lookup, reading energies from the
+// search grid instead of the records (validation path, LDS staging).
 
 struct GridRec {
   double e;
 };
+
+template <int GRID>
+__device__ __forceinline__ int exact_bracket(const DevTables& t,
+                                             const Locator<GRID>& loc,
+                                             const MatRec& r, int j,
+                                             double e) {
+  const int cand = loc.start(t, r, j, e);
+  if (GRID != XS_GRID_HASH) return cand;
+  const double* g = t.E + r.base;
+  const GridRec g0{g[cand]}, g1{g[cand + 1]}, g2{g[min(cand + 2, r.n - 1)]};
+  const bool up = cand + 1 <= r.n - 2 && g1.e <= e;
+  const int i = up ? cand + 1 : cand;
+  const GridRec lo{up ? g1.e : g0.e}, hi{up ? g2.e : g1.e};
+  if (bracket_ok(i, r.n, e, lo, hi)) return i;
+  return hash_slow(t, r, loc.next_row(t), cand, e);
+}
 
 template <int GRID>
 __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
@@ -526,27 +542,123 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
   }
   Locator<GRID> loc;
   loc.init(t, e, m);
-  for (int j = j0; j < j1; ++j) {
-    const MatRec r = t.mrec[j];
-    const int cand = loc.start(t, r, j, e);
-    int i = cand;
-    if (GRID == XS_GRID_HASH) {
-      const double* g = t.E + r.base;
-      const GridRec g0{g[cand]}, g1{g[cand + 1]}, g2{g[min(cand + 2, r.n - 1)]};
-      GridRec lo, hi;
-      if (cand + 1 <= r.n - 2 && g1.e <= e) {
-        i = cand + 1;
-        lo = g1;
-        hi = g2;
-      } else {
-        lo = g0;
-        hi = g1;
-      }
-      if (!bracket_ok(i, r.n, e, lo, hi))
-        i = hash_slow(t, r, loc.next_row(t), cand, e);
-    }
-    out[j - j0] = i;
+  for (int j = j0; j < j1; ++j) out[j - j0] = exact_bracket(t, loc, t.mrec[j], j, e);
+}
+
+// ---- LDS-staged lookup -------------------------------------------------------------
+//
+// For a block whose lookups all share one material (the usual case after a
+// sort), each nuclide's brackets lie between those of the block's lowest and
+// highest energies.  Two lanes find those two brackets, the block loads the
+// records in between into LDS with one cooperative read, and every lane
+// bisects and interpolates from LDS.  A window wider than kStageCap records,
+// or a block holding several materials, takes the per-lane path.  Same
+// arithmetic, same order: the sums are bit-identical to k_lookup's.
+
+constexpr int kStageCap = 64;
+
+template <int GRID, int PREC>
+__global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
+                                                     const LookupArgs a) {
+  using R = typename RecOf<PREC>::T;
+  __shared__ R stage[kStageCap];
+  __shared__ int s_mat, s_win[2];
+  __shared__ double s_red[2][16];
+  const int tid = threadIdx.x;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t n = a.count_dev ? *a.count_dev : a.n;
+  const int64_t q = blk * (int64_t)blockDim.x + tid;
+
+  bool act = q < n;
+  int64_t o = 0;
+  double e = 1.0;
+  int m = -1;
+  if (act) {
+    o = a.perm ? (int64_t)a.perm[q] : q;
+    if ((uint64_t)o >= (uint64_t)a.n) act = false;
+    else if (a.active && !a.active[o]) act = false;
   }
+  if (act) {
+    e = a.E[o];
+    m = a.mat[o];
+    if (!valid_query(e, m, t.M)) {
+      Acc<PREC>::store_nan(a.out, o);
+      act = false;
+    }
+  }
+  if (tid == 0) s_mat = act ? m : -1;
+  __syncthreads();
+  const int mb = s_mat;
+  const bool uniform = __syncthreads_and(act && m == mb && mb >= 0);
+
+  Locator<GRID> loc;
+  Acc<PREC> acc;
+  loc.init(t, e, m);
+  acc.zero();
+  if (!uniform) {
+    if (act) {
+      const double e1[1] = {e};
+      Locator<GRID> l1[1] = {loc};
+      Acc<PREC> a1[1];
+      a1[0].zero();
+      walk_material<GRID, PREC, 1, 1>(t, m, e1, l1, a1);
+      a1[0].store(a.out, o);
+    }
+    return;
+  }
+
+  // Block energy range (all lanes active here).
+  double lo_e = e, hi_e = e;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    lo_e = fmin(lo_e, __shfl_xor(lo_e, off, 64));
+    hi_e = fmax(hi_e, __shfl_xor(hi_e, off, 64));
+  }
+  const int w = tid >> 6, lane = tid & 63, nw = (blockDim.x + 63) >> 6;
+  if (lane == 0) {
+    s_red[0][w] = lo_e;
+    s_red[1][w] = hi_e;
+  }
+  __syncthreads();
+  lo_e = s_red[0][0];
+  hi_e = s_red[1][0];
+  for (int i = 1; i < nw; ++i) {
+    lo_e = fmin(lo_e, s_red[0][i]);
+    hi_e = fmax(hi_e, s_red[1][i]);
+  }
+  Locator<GRID> edge = loc;  // lanes 0 and 1: the block's lowest / highest E
+  if (tid < 2) edge.init(t, tid == 0 ? lo_e : hi_e, mb);
+
+  const R* recs = RecOf<PREC>::base(t);
+  const int j0 = ld_const(t.moff + mb), j1 = ld_const(t.moff + mb + 1);
+  for (int j = j0; j < j1; ++j) {
+    const MatRec r = ld_const(t.mrec + j);
+    if (tid < 2) s_win[tid] = exact_bracket(t, edge, r, j, tid == 0 ? lo_e : hi_e);
+    __syncthreads();
+    const int ilo = s_win[0], width = s_win[1] - ilo + 2;
+    const auto rho = Acc<PREC>::rho(t, r, j);
+    if (width <= kStageCap) {
+      if (tid < width) stage[tid] = recs[r.base + ilo + tid];
+      __syncthreads();
+      // largest p in [0, width-2] with stage[p].e <= e, else 0
+      int p = 0, len = width - 1;
+      while (len > 1) {
+        const int half = len >> 1;
+        p = (stage[p + half].e <= e) ? p + half : p;
+        len -= half;
+      }
+      acc.add(stage[p], stage[p + 1], e, rho);
+    } else {
+      const int cand = loc.start(t, r, j, e);
+      Window<GRID, PREC> win;
+      win.load(t, r, cand);
+      R lo, hi;
+      win.finish(t, r, loc, cand, e, lo, hi);
+      acc.add(lo, hi, e, rho);
+    }
+    __syncthreads();  // stage and s_win are rewritten for the next nuclide
+  }
+  acc.store(a.out, o);
 }
 
 // ---- launchers ------------------------------------------------------------------
@@ -585,6 +697,19 @@ hipError_t launch_variant(const DevTables& t, int lpt, int unroll, dim3 grid,
 template <int GRID>
 hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
                               const LookupArgs& a, hipStream_t s) {
+  if (p.lds_stage) {
+    if (p.lookups_per_thread != 1 || p.unroll != 1) return hipErrorInvalidValue;
+    const int64_t nb = (a.n + p.block_size - 1) / p.block_size;
+    if (nb == 0) return hipSuccess;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (p.precision == XS_FP64)
+      hipLaunchKernelGGL((k_lookup_lds<GRID, XS_FP64>), dim3((unsigned)nb),
+                         dim3(p.block_size), 0, s, t, a);
+    else
+      hipLaunchKernelGGL((k_lookup_lds<GRID, XS_FP32>), dim3((unsigned)nb),
+                         dim3(p.block_size), 0, s, t, a);
+    return hipGetLastError();
+  }
   if (!variant_exists(p.lookups_per_thread, p.unroll) ||
       p.block_size > max_block_for(p.lookups_per_thread, p.unroll))
     return hipErrorInvalidValue;

@@ -13,8 +13,8 @@
 // in section 5.2): the sort threshold is inactive without a sort.
 //
 // Here the space is the lookup's own: grid method x sort policy x block size
-// x (lookups per lane, nuclides in flight), with invalid combinations
-// removed.  For a fixed batch size the threshold only decides whether the
+// x (lookups per lane, nuclides in flight, or LDS staging), with invalid
+// combinations removed.  For a fixed batch size the threshold only decides whether the
 // sort runs, which the sort policy NONE already expresses, so it is 0 for
 // every sorting candidate.
 #include <hip/hip_runtime_api.h>
@@ -34,7 +34,7 @@ namespace {
 
 // ---- the configuration space ---------------------------------------------
 
-constexpr int kNumFeatures = 12;
+constexpr int kNumFeatures = 13;
 
 struct Cand {
   xs_params p;
@@ -52,13 +52,17 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
   static const int kVariants[][2] = {{1, 1}, {2, 1}, {3, 1}, {4, 1}, {5, 1},
                                      {6, 1}, {7, 1}, {8, 1}, {1, 2}, {2, 2},
                                      {1, 4}, {2, 4}};
+  constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
   std::vector<Cand> out;
   for (int g = 0; g < 3; ++g) {
     if (!(grids >> g & 1u)) continue;
     for (int s = 0; s < 5; ++s) {
       if (!(sorts >> s & 1u)) continue;
       for (int b : kBlocks) {
-        for (auto& v : kVariants) {
+        for (int vi = 0; vi <= kNumVariants; ++vi) {
+          // the last variant is LDS staging (one lookup, one nuclide per lane)
+          const bool lds = vi == kNumVariants;
+          const int v[2] = {lds ? 1 : kVariants[vi][0], lds ? 1 : kVariants[vi][1]};
           if (b > max_block(v[0], v[1])) continue;
           Cand c{};
           c.p.precision = precision;
@@ -67,7 +71,7 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
           c.p.block_size = b;
           c.p.lookups_per_thread = v[0];
           c.p.unroll = v[1];
-          c.p.lds_stage = 0;
+          c.p.lds_stage = lds ? 1 : 0;
           c.p.sort_threshold =
               s == XS_SORT_NONE ? std::numeric_limits<int64_t>::max() : 0;
           c.p.queue = XS_QUEUE_COMPACT;
@@ -77,6 +81,7 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
           c.f[9] = (float)v[0];
           c.f[10] = (float)v[1];
           c.f[11] = (float)(v[0] * v[1]);
+          c.f[12] = lds ? 1.f : 0.f;
           out.push_back(c);
         }
       }
@@ -100,26 +105,26 @@ struct Rng {
 
 // ---- random-forest regressor ---------------------------------------------
 //
-// Bootstrap-sampled CART trees grown on squared error, each split chosen
-// among a random subset of the features (8 of 12; nodes under 4 samples stay
-// leaves); the forest's mean is the prediction and the spread of the trees'
-// predictions its uncertainty.
+// Bootstrap-sampled CART trees grown on squared error (all features tried
+// at every split, nodes under 6 samples stay leaves); the forest's mean is
+// the prediction.
 
 struct Node {
   int feature = -1;  // -1: leaf
   float threshold = 0.f;
   int left = -1, right = -1;
-  double value = 0.0;
+  double value = 0.0;  // mean of the node's training targets
+  double var = 0.0;    // their variance
 };
 
 struct Tree {
   std::vector<Node> nodes;
-  double predict(const float* x) const {
+  const Node& leaf(const float* x) const {
     int i = 0;
     while (nodes[i].feature >= 0)
       i = x[nodes[i].feature] <= nodes[i].threshold ? nodes[i].left
                                                      : nodes[i].right;
-    return nodes[i].value;
+    return nodes[i];
   }
 };
 
@@ -139,12 +144,16 @@ class Forest {
     }
   }
 
+  // Mean over trees, and the standard deviation by the law of total
+  // variance: the spread of the trees' leaf means plus the variance of the
+  // targets inside each leaf (Hutter et al., "Algorithm runtime prediction",
+  // 2014), so that leaves pooling unlike configurations stay uncertain.
   void predict(const float* x, double* mean, double* sd) const {
     double s = 0, s2 = 0;
     for (auto& t : forest_) {
-      const double v = t.predict(x);
-      s += v;
-      s2 += v * v;
+      const Node& l = t.leaf(x);
+      s += l.value;
+      s2 += l.var + l.value * l.value;
     }
     const double m = s / forest_.size();
     *mean = m;
@@ -156,10 +165,15 @@ class Forest {
            const std::vector<double>& y, std::vector<size_t>& idx, int depth) {
     const int id = (int)t.nodes.size();
     t.nodes.emplace_back();
-    double sum = 0;
-    for (size_t i : idx) sum += y[i];
-    t.nodes[id].value = sum / idx.size();
-    if (depth >= max_depth_ || idx.size() < 4) return id;
+    double sum = 0, sum2 = 0;
+    for (size_t i : idx) {
+      sum += y[i];
+      sum2 += y[i] * y[i];
+    }
+    const double mu = sum / idx.size();
+    t.nodes[id].value = mu;
+    t.nodes[id].var = std::max(0.0, sum2 / idx.size() - mu * mu);
+    if (depth >= max_depth_ || idx.size() < 6) return id;
 
     // Random feature subset.
     int feats[kNumFeatures];
@@ -216,7 +230,8 @@ class Forest {
 
 bool same_choice(const xs_params& a, const xs_params& b) {
   return a.grid == b.grid && a.sort == b.sort && a.block_size == b.block_size &&
-         a.lookups_per_thread == b.lookups_per_thread && a.unroll == b.unroll;
+         a.lookups_per_thread == b.lookups_per_thread && a.unroll == b.unroll &&
+         a.lds_stage == b.lds_stage;
 }
 
 // ---- the search ---------------------------------------------------------------
@@ -343,7 +358,7 @@ xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
         X.push_back(S.space[c].f);
         y.push_back(S.obj[c]);
       }
-      Forest forest(64, 8, 12, rng.next());
+      Forest forest(64, kNumFeatures, 12, rng.next());
       forest.fit(X, y);
       std::vector<std::pair<double, int>> acq;
       for (int i = 0; i < N; ++i) {

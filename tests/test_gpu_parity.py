@@ -112,6 +112,12 @@ KNOBS = [
          lookups_per_thread=7),
     dict(sort="energy", sort_threshold=0, block_size=256, lookups_per_thread=2,
          unroll=4),
+    dict(sort="band_material", sort_threshold=0, block_size=256,
+         lookups_per_thread=1, unroll=1, lds_stage=1),
+    dict(sort="none", block_size=128, lookups_per_thread=1, unroll=1,
+         lds_stage=1),
+    dict(sort="material_energy", sort_threshold=0, block_size=1024,
+         lookups_per_thread=1, unroll=1, lds_stage=1),
 ]
 
 
@@ -239,7 +245,9 @@ def test_errors_from_device_calls(cfg1):
     for bad in (dict(block_size=1024, lookups_per_thread=5),
                 dict(block_size=1024, lookups_per_thread=2, unroll=2),
                 dict(lookups_per_thread=3, unroll=2), dict(unroll=3),
-                dict(sort=5), dict(grid=3), dict(lds_stage=2)):
+                dict(sort=5), dict(grid=3), dict(lds_stage=2),
+                dict(lds_stage=1, lookups_per_thread=2),
+                dict(lds_stage=1, unroll=2)):
         with pytest.raises(xs.XsError) as e:
             xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
                                params=xs.make_params(**bad))
