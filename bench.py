@@ -125,6 +125,135 @@ def cpu_baseline(tables, q, seconds: float) -> dict:
                       f"{dt:.1f} s"}
 
 
+def _pctl(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(round(q * (len(v) - 1))))] if v else 0.0
+
+
+def sweep_in_flight(args, torch, synth, xs):
+    """Config 4: batches of 1e5 ... 8e6 lookups on the full-size tables; per
+    batch size the FP32 form is tuned (forest search) and timed, beside the
+    plain FP64 lookup and the FP32 form under each sort policy at the tuned
+    launch shape.  One JSON line per batch size."""
+    t = synth.config2_tables()
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    h = xs.xs_create_tables(t, flags, args.bins)
+    for i, n in enumerate((100_000, 500_000, 1_000_000, 2_000_000, 4_000_000,
+                           8_000_000)):
+        q = synth.config4_queries(i, n)
+        E = torch.from_numpy(q.E).to("cuda:0")
+        m = torch.from_numpy(q.mat).to("cuda:0")
+        nbar = synth.mean_nuclides(t, q)
+        ws = xs._workspace(xs.xs_workspace_size(h, n, xs.make_params(
+            sort="band_material", sort_threshold=0)), E.device)
+
+        def rate(p):
+            out = torch.empty((n, 5), device="cuda:0", dtype=torch.float64
+                              if p.precision == 0 else torch.float32)
+            sec = time_steps(lambda: xs.xs_lookup_batch(
+                h, E, m, out=out, params=p, workspace=ws),
+                args.steps, args.warmup)
+            return n / sec
+
+        cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
+                                        max_evals=args.tune_evals, reps=3)
+        r = xs.xs_tune(h, E, m, cfg, workspace=ws)
+        best = r.best
+        row = {"n": n, "mean_nuclides": nbar, "tuned": best.as_dict(),
+               "tuned_lookups_per_s": rate(best),
+               "tuner": {"evaluated": r.evaluated, "cut": r.cut,
+                         "best_eval": r.best_eval}}
+        plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
+                               block_size=256, lookups_per_thread=1, unroll=1,
+                               lds_stage=0, sort_threshold=xs.INT64_MAX)
+        row["plain_fp64_lookups_per_s"] = rate(plain)
+        for name, sp in xs.SORTS.items():
+            p = xs.xs_params()
+            p.precision, p.grid, p.sort = best.precision, best.grid, sp
+            p.block_size, p.lookups_per_thread = best.block_size, best.lookups_per_thread
+            p.unroll, p.lds_stage, p.queue = best.unroll, best.lds_stage, best.queue
+            p.sort_threshold = 0 if sp else xs.INT64_MAX
+            row[f"fp32_sort_{name}_lookups_per_s"] = rate(p)
+        print(json.dumps(row), flush=True)
+        log(f"n={n}: tuned {row['tuned_lookups_per_s']:.4g}/s "
+            f"({best.as_dict()}), plain FP64 {row['plain_fp64_lookups_per_s']:.4g}/s")
+    h.close()
+    return 0
+
+
+def request_stream(args, torch, synth, xs):
+    """Config 5: an uneven stream of requests (sizes log-uniform in
+    [1e3, 1e6], energies 70 % log-uniform and 30 % from narrow peaks) served
+    by one persistent graph-launched kernel, against one xs_lookup_batch
+    launch per request with parameters tuned per size class."""
+    t = synth.config2_tables()
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    h = xs.xs_create_tables(t, flags, args.bins)
+    log("generating the request stream")
+    sizes, q = synth.config5_requests(args.stream_requests)
+    total = int(sizes.sum())
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    out = torch.empty((total, 5), device="cuda:0", dtype=torch.float32)
+    offs = np.concatenate(([0], np.cumsum(sizes)))
+    log(f"{len(sizes)} requests, {total} lookups")
+
+    # Tune the FP32 form per size class (10^3 .. 10^6) on slices of the stream.
+    for n in (1_000, 10_000, 100_000, 1_000_000):
+        cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
+                                        max_evals=args.tune_evals, reps=3)
+        r = xs.xs_tune(h, E[:n], m[:n], cfg)
+        log(f"tuned class {n}: {r.best.as_dict()} {r.best_ms:.3f} ms")
+    reqs = [(E[a:b], m[a:b], out[a:b]) for a, b in zip(offs[:-1], offs[1:])]
+
+    # Per-request launches, HIP events around each call.
+    ws = xs._workspace(xs.xs_workspace_size(h, int(sizes.max()),
+                       xs.make_params(xs.XS_FP32, sort="band_material",
+                                      sort_threshold=0)), E.device)
+    p_auto = xs.xs_params_default(xs.XS_FP32)
+    st = torch.cuda.current_stream()
+    best_launch = None
+    for rep in range(max(1, args.steps // 5) + 1):
+        evs = [(torch.cuda.Event(enable_timing=True),
+                torch.cuda.Event(enable_timing=True)) for _ in reqs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (e0, e1), (Er, mr, orr) in zip(evs, reqs):
+            e0.record(st)
+            xs.xs_lookup_batch(h, Er, mr, out=orr, params=p_auto, workspace=ws)
+            e1.record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = [a.elapsed_time(b) * 1e3 for a, b in evs]
+        if rep > 0 and (best_launch is None or wall < best_launch["wall_s"]):
+            best_launch = {"wall_s": wall, "lookups_per_s": total / wall,
+                           "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
+    # One persistent kernel per batch of requests.
+    p_stream = xs.xs_resolve_params(h, 1_000_000, p_auto)
+    s = xs.xs_stream_create(h, p_stream, max_requests=len(reqs))
+    best_stream = None
+    for rep in range(max(1, args.steps // 5) + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs.xs_stream_submit(s, reqs)
+        stats, makespan = xs.xs_stream_wait(s)
+        wall = time.perf_counter() - t0
+        lat = [r["latency_us"] for r in stats]
+        if rep > 0 and (best_stream is None or wall < best_stream["wall_s"]):
+            best_stream = {"wall_s": wall, "lookups_per_s": total / wall,
+                           "device_makespan_us": makespan,
+                           "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
+    s.close()
+    print(json.dumps({"config": "uneven request stream", "requests": len(reqs),
+                      "lookups": total, "per_request_launches": best_launch,
+                      "persistent_graph_kernel": best_stream,
+                      "stream_params": p_stream.as_dict()}), flush=True)
+    h.close()
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +273,10 @@ def main(argv=None):
                     default="forest")
     ap.add_argument("--only", choices=["plain", "tuned"], default=None,
                     help="time one form only (for profiling runs)")
+    ap.add_argument("--config", type=int, choices=[2, 4, 5], default=2,
+                    help="2: the headline line (default); 4: particles-in-"
+                         "flight sweep; 5: uneven request stream")
+    ap.add_argument("--stream-requests", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 GiB and exit (the "
                          "achievable-bandwidth figure and the reference for "
@@ -170,6 +303,11 @@ def main(argv=None):
                           "gbs_read_plus_write": 2 * nbytes / sec / 1e9}),
               flush=True)
         return 0
+
+    if args.config == 4:
+        return sweep_in_flight(args, torch, synth, xs)
+    if args.config == 5:
+        return request_stream(args, torch, synth, xs)
 
     log("generating config-2 tables and queries")
     t = synth.config2_tables()
