@@ -373,6 +373,25 @@ xs_status xs_stream_params(xs_stream_t s, xs_params* out);
 /* Waits for any batch in flight and frees the stream.  NULL is a no-op. */
 xs_status xs_stream_destroy(xs_stream_t s);
 
+/* One launch for a batch of requests (HOST array of count descriptors, read
+ * during the call): the grid has one 256-lane block per 1024-lookup tile of
+ * the batch; each block sorts its tile in LDS by material and energy, looks
+ * it up and stamps the request's first and last tile with the device wall
+ * clock.  params as for xs_stream_create.  d_ws: DEVICE, 256-byte aligned, at
+ * least xs_requests_workspace_size(count) bytes; it holds the descriptors and
+ * stamps until xs_requests_stats reads them.  Results equal xs_lookup_batch's
+ * bit for bit. */
+xs_status xs_lookup_requests(xs_tables_t tables, const xs_request* reqs,
+                             int32_t count, const xs_params* params,
+                             void* d_ws, size_t ws_bytes, void* stream);
+
+xs_status xs_requests_workspace_size(int32_t count, size_t* bytes);
+
+/* Synchronises `stream` and reads the per-request times of the last
+ * xs_lookup_requests call that used d_ws (stats[count] may be NULL). */
+xs_status xs_requests_stats(const void* d_ws, int32_t count, void* stream,
+                            xs_request_stats* stats, double* makespan_us);
+
 /* ---- measurement --------------------------------------------------------- */
 
 /* Starts recording per-stage HIP events for subsequent lookup calls on this

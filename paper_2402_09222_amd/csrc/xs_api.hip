@@ -49,6 +49,13 @@ void release(xs_tables_s* h) {
   for (auto& c : h->prof)
     for (hipEvent_t e : c.ev) (void)hipEventDestroy(e);
   h->prof.clear();
+  if (h->req_event) {
+    (void)hipEventSynchronize(h->req_event);
+    (void)hipEventDestroy(h->req_event);
+    h->req_event = nullptr;
+  }
+  if (h->req_stage) (void)hipHostFree(h->req_stage);
+  h->req_stage = nullptr;
 }
 
 template <class T>

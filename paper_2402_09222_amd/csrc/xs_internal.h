@@ -106,6 +106,11 @@ struct xs_tables_s {
   bool profiling = false;
   std::vector<xs::ProfCall> prof;
   std::vector<hipEvent_t> event_pool;
+  // pinned staging of request descriptors (xs_lookup_requests); the event
+  // marks the end of the last copy out of it
+  void* req_stage = nullptr;
+  size_t req_stage_bytes = 0;
+  hipEvent_t req_event = nullptr;
 };
 
 namespace xs {

@@ -71,6 +71,87 @@ __global__ void k_stream_init(StreamState* st, unsigned long long* t_first,
   }
 }
 
+// Sorts the tile's lookups in LDS by (material, energy) and looks them up:
+// lane tid takes sorted positions tid, tid + 256, ...  Called by all 256
+// lanes of the block; the caller synchronises before reusing skey/sidx.
+template <int GRID, int PREC, int U>
+__device__ __forceinline__ void process_tile(const DevTables& t,
+                                             const ReqDev& R, int64_t base,
+                                             uint32_t* skey, uint16_t* sidx,
+                                             int64_t ebits_min, int eshift) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int p = 0; p < kPerLane; ++p) {
+    const int pos = tid + p * kStreamThreads;
+    const int64_t q = base + pos;
+    uint32_t key = 0xffffffffu;
+    if (q < R.n) key = tile_key(R.E[q], R.mat[q], t.M, ebits_min, eshift);
+    skey[pos] = key;
+    sidx[pos] = (uint16_t)pos;
+  }
+  __syncthreads();
+  // Bitonic network over the 1024 (key, position) pairs.
+  for (int k = 2; k <= kStreamTile; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int p = 0; p < kPerLane / 2; ++p) {
+        const int i = tid + p * kStreamThreads;  // pair (a, a + j), bit j of a clear
+        const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+        const int b = a | j;
+        const bool up = (a & k) == 0;
+        const uint32_t ka = skey[a], kb = skey[b];
+        if ((ka > kb) == up) {
+          skey[a] = kb;
+          skey[b] = ka;
+          const uint16_t t2 = sidx[a];
+          sidx[a] = sidx[b];
+          sidx[b] = t2;
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll 1
+  for (int p = 0; p < kPerLane; ++p) {
+    const int pos = tid + p * kStreamThreads;
+    const int64_t q = base + sidx[pos];
+    const bool act = q < R.n;
+    double e = 1.0;
+    int m = -1;
+    if (act) {
+      e = R.E[q];
+      m = R.mat[q];
+    }
+    const bool ok = act && valid_query(e, m, t.M);
+    if (act && !ok) Acc<PREC>::store_nan(R.out, q);
+    const int mu = __builtin_amdgcn_readfirstlane(m);
+    const bool wave_uniform = __all(ok && m == mu);
+    if (ok) {
+      const double e1[1] = {e};
+      Locator<GRID> loc[1];
+      Acc<PREC> acc[1];
+      loc[0].init(t, e, m);
+      acc[0].zero();
+      if (wave_uniform)
+        walk_material<GRID, PREC, 1, U>(t, mu, e1, loc, acc);
+      else
+        walk_material<GRID, PREC, 1, U>(t, m, e1, loc, acc);
+      acc[0].store(R.out, q);
+    }
+  }
+}
+
+// Request of global tile g: largest r < count with tile_begin <= g.
+__device__ __forceinline__ int request_of(const ReqDev* reqs, int count,
+                                          int64_t g) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (reqs[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 template <int GRID, int PREC, int U>
 __global__ __launch_bounds__(kStreamThreads) void k_stream(
     const DevTables t, const StreamHeader* __restrict__ hdr,
@@ -91,86 +172,53 @@ __global__ __launch_bounds__(kStreamThreads) void k_stream(
     __syncthreads();
     if (g >= tiles) break;  // every block reaches this once the batch is done
     const unsigned long long t0 = wall_clock64();
-
-    // Request holding tile g (largest r with tile_begin <= g).
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (reqs[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
-    }
-    const ReqDev R = reqs[lo];
-    const int64_t base = (g - R.tile_begin) * kStreamTile;
-
-    // Load and key the tile, then sort it in LDS (bitonic network).
-#pragma unroll
-    for (int p = 0; p < kPerLane; ++p) {
-      const int pos = tid + p * kStreamThreads;
-      const int64_t q = base + pos;
-      uint32_t key = 0xffffffffu;
-      if (q < R.n) key = tile_key(R.E[q], R.mat[q], t.M, ebits_min, eshift);
-      skey[pos] = key;
-      sidx[pos] = (uint16_t)pos;
-    }
-    __syncthreads();
-    for (int k = 2; k <= kStreamTile; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-        for (int p = 0; p < kPerLane / 2; ++p) {
-          // pair (a, a ^ j) with a's bit j clear
-          const int i = tid + p * kStreamThreads;
-          const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-          const int b = a | j;
-          const bool up = (a & k) == 0;
-          const uint32_t ka = skey[a], kb = skey[b];
-          if ((ka > kb) == up) {
-            skey[a] = kb;
-            skey[b] = ka;
-            const uint16_t t2 = sidx[a];
-            sidx[a] = sidx[b];
-            sidx[b] = t2;
-          }
-        }
-        __syncthreads();
-      }
-    }
-
-    // Look up in sorted order: lane tid takes sorted positions tid, tid+256..
-#pragma unroll 1
-    for (int p = 0; p < kPerLane; ++p) {
-      const int pos = tid + p * kStreamThreads;
-      const int64_t q = base + sidx[pos];
-      const bool act = q < R.n;
-      double e = 1.0;
-      int m = -1;
-      if (act) {
-        e = R.E[q];
-        m = R.mat[q];
-      }
-      const bool ok = act && valid_query(e, m, t.M);
-      if (act && !ok) Acc<PREC>::store_nan(R.out, q);
-      const int mu = __builtin_amdgcn_readfirstlane(m);
-      const bool wave_uniform = __all(ok && m == mu);
-      if (ok || wave_uniform) {
-        const double e1[1] = {e};
-        Locator<GRID> loc[1];
-        Acc<PREC> acc[1];
-        loc[0].init(t, e, m);
-        acc[0].zero();
-        if (wave_uniform)
-          walk_material<GRID, PREC, 1, U>(t, mu, e1, loc, acc);
-        else
-          walk_material<GRID, PREC, 1, U>(t, m, e1, loc, acc);
-        acc[0].store(R.out, q);
-      }
-    }
+    const int r = request_of(reqs, count, g);
+    const ReqDev R = reqs[r];
+    process_tile<GRID, PREC, U>(t, R, (g - R.tile_begin) * kStreamTile, skey,
+                                sidx, ebits_min, eshift);
     __syncthreads();  // the tile's LDS is reused by the next claim
     if (tid == 0) {
       const unsigned long long t1 = wall_clock64();
-      atomicMin(&t_first[lo], t0);
-      atomicMax(&t_last[lo], t1);
+      atomicMin(&t_first[r], t0);
+      atomicMax(&t_last[r], t1);
       atomicMin(&st->t_min, t0);
     }
   }
+}
+
+// One launch for a batch of requests: block b processes global tile b (the
+// grid is exactly the batch's tile count, computed on the host), so no block
+// waits on or loops over anything read from device memory.
+template <int GRID, int PREC, int U>
+__global__ __launch_bounds__(kStreamThreads) void k_requests(
+    const DevTables t, const ReqDev* __restrict__ reqs, int count,
+    unsigned long long* stamps, int64_t ebits_min, int eshift) {
+  __shared__ uint32_t skey[kStreamTile];
+  __shared__ uint16_t sidx[kStreamTile];
+  const int64_t g = blockIdx.x;
+  const unsigned long long t0 = wall_clock64();
+  const int r = request_of(reqs, count, g);
+  const ReqDev R = reqs[r];
+  process_tile<GRID, PREC, U>(t, R, (g - R.tile_begin) * kStreamTile, skey,
+                              sidx, ebits_min, eshift);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t1 = wall_clock64();
+    atomicMin(&stamps[2 * r], t0);
+    atomicMax(&stamps[2 * r + 1], t1);
+    atomicMin(&stamps[2 * count], t0);
+  }
+}
+
+// stamps[2r] = first start (init: max), stamps[2r+1] = last end (init: 0),
+// stamps[2*count] = batch start.
+__global__ void k_requests_init(unsigned long long* stamps, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    stamps[2 * i] = ~0ull;
+    stamps[2 * i + 1] = 0;
+  }
+  if (i == 0) stamps[2 * count] = ~0ull;
 }
 
 }  // namespace
@@ -419,6 +467,184 @@ xs_status xs_stream_destroy(xs_stream_t s) {
   if (!s) return XS_OK;
   if (s->pending) (void)hipEventSynchronize(s->done);
   stream_release(s);
+  return XS_OK;
+}
+
+}  // extern "C"
+
+// ---- one launch for a batch of requests ------------------------------------
+
+namespace xs {
+namespace {
+
+size_t align256b(size_t b) { return (b + 255) & ~size_t(255); }
+
+template <int GRID, int PREC, int U>
+hipError_t launch_requests_kernel(const DevTables& t, const ReqDev* reqs,
+                                  int count, unsigned long long* stamps,
+                                  int64_t tiles, int64_t bmin, int shift,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL((k_requests<GRID, PREC, U>), dim3((unsigned)tiles),
+                     dim3(kStreamThreads), 0, s, t, reqs, count, stamps, bmin,
+                     shift);
+  return hipGetLastError();
+}
+
+template <int GRID, int PREC>
+hipError_t launch_requests_u(const xs_params& p, const DevTables& t,
+                             const ReqDev* reqs, int count,
+                             unsigned long long* stamps, int64_t tiles,
+                             int64_t bmin, int shift, hipStream_t s) {
+  switch (p.unroll) {
+    case 1: return launch_requests_kernel<GRID, PREC, 1>(t, reqs, count, stamps, tiles, bmin, shift, s);
+    case 2: return launch_requests_kernel<GRID, PREC, 2>(t, reqs, count, stamps, tiles, bmin, shift, s);
+    default: return launch_requests_kernel<GRID, PREC, 4>(t, reqs, count, stamps, tiles, bmin, shift, s);
+  }
+}
+
+template <int GRID>
+hipError_t launch_requests_p(const xs_params& p, const DevTables& t,
+                             const ReqDev* reqs, int count,
+                             unsigned long long* stamps, int64_t tiles,
+                             int64_t bmin, int shift, hipStream_t s) {
+  return p.precision == XS_FP64
+             ? launch_requests_u<GRID, XS_FP64>(p, t, reqs, count, stamps, tiles, bmin, shift, s)
+             : launch_requests_u<GRID, XS_FP32>(p, t, reqs, count, stamps, tiles, bmin, shift, s);
+}
+
+void energy_key_shift(const xs_tables_s* h, int64_t* bmin, int* shift) {
+  int64_t lo, hi;
+  std::memcpy(&lo, &h->info.e_min, 8);
+  std::memcpy(&hi, &h->info.e_max, 8);
+  int sh = 0;
+  while (((hi - lo) >> sh) > 0xffff) ++sh;
+  *bmin = lo;
+  *shift = sh;
+}
+
+}  // namespace
+}  // namespace xs
+
+extern "C" {
+
+xs_status xs_requests_workspace_size(int32_t count, size_t* bytes) {
+  clear_error();
+  if (!bytes || count < 1) return fail(XS_EINVAL, "count >= 1 and bytes needed");
+  *bytes = align256b(sizeof(ReqDev) * (size_t)count) +
+           align256b(8 * (2 * (size_t)count + 1));
+  return XS_OK;
+}
+
+xs_status xs_lookup_requests(xs_tables_t h, const xs_request* reqs,
+                             int32_t count, const xs_params* params,
+                             void* d_ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!h) return fail(XS_EINVAL, "table handle is NULL");
+  if (count < 1 || count > (1 << 24) || !reqs)
+    return fail(XS_EINVAL, "count must be in [1, 2^24] and reqs not NULL");
+  xs_params p;
+  if (xs_status st = xs_resolve_params(h, 1 << 20, params, &p)) return st;
+  size_t need = 0;
+  xs_requests_workspace_size(count, &need);
+  if (!d_ws || ws_bytes < need || (uintptr_t)d_ws % 256)
+    return fail(XS_EWORKSPACE, "a 256-byte aligned workspace of %zu bytes is "
+                "needed", need);
+  int dev = -1;
+  XS_HIP(hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(XS_EINVAL, "current device %d is not the tables' device %d",
+                dev, h->device);
+  hipStream_t s = (hipStream_t)stream;
+  ReqDev* reqs_dev = (ReqDev*)d_ws;
+  auto* stamps = (unsigned long long*)((char*)d_ws +
+                                      align256b(sizeof(ReqDev) * (size_t)count));
+  int64_t tiles = 0;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    const size_t bytes = sizeof(ReqDev) * (size_t)count;
+    if (h->req_event) XS_HIP(hipEventSynchronize(h->req_event));
+    if (h->req_stage_bytes < bytes) {
+      if (h->req_stage) XS_HIP(hipHostFree(h->req_stage));
+      h->req_stage = nullptr;
+      h->req_stage_bytes = 0;
+      XS_HIP(hipHostMalloc(&h->req_stage, bytes));
+      h->req_stage_bytes = bytes;
+    }
+    if (!h->req_event) XS_HIP(hipEventCreateWithFlags(&h->req_event,
+                                                      hipEventDisableTiming));
+    auto* rd = (ReqDev*)h->req_stage;
+    for (int i = 0; i < count; ++i) {
+      const xs_request& r = reqs[i];
+      if (r.n < 0 || r.n > 0x7fffffffLL)
+        return fail(XS_EINVAL, "request %d: n out of range", i);
+      if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
+        return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
+      rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles};
+      tiles += (r.n + kStreamTile - 1) / kStreamTile;
+    }
+    if (tiles > 0x7fffffffLL) return fail(XS_EINVAL, "batch too large");
+    XS_HIP(hipMemcpyAsync(reqs_dev, rd, bytes, hipMemcpyHostToDevice, s));
+    XS_HIP(hipEventRecord(h->req_event, s));
+  }
+  hipLaunchKernelGGL(k_requests_init, dim3((count + 1 + 255) / 256), dim3(256),
+                     0, s, stamps, count);
+  XS_HIP(hipGetLastError());
+  if (tiles == 0) return XS_OK;
+  int64_t bmin;
+  int shift;
+  energy_key_shift(h, &bmin, &shift);
+  hipError_t e;
+  switch (p.grid) {
+    case XS_GRID_NUCLIDE:
+      e = launch_requests_p<XS_GRID_NUCLIDE>(p, h->d, reqs_dev, count, stamps, tiles, bmin, shift, s);
+      break;
+    case XS_GRID_HASH:
+      e = launch_requests_p<XS_GRID_HASH>(p, h->d, reqs_dev, count, stamps, tiles, bmin, shift, s);
+      break;
+    default:
+      e = launch_requests_p<XS_GRID_UNIONIZED>(p, h->d, reqs_dev, count, stamps, tiles, bmin, shift, s);
+      break;
+  }
+  if (e != hipSuccess)
+    return fail(XS_EHIP, "request kernel launch failed: %s", hipGetErrorString(e));
+  return XS_OK;
+}
+
+xs_status xs_requests_stats(const void* d_ws, int32_t count, void* stream,
+                            xs_request_stats* stats, double* makespan_us) {
+  clear_error();
+  if (!d_ws || count < 1) return fail(XS_EINVAL, "workspace and count needed");
+  hipStream_t s = (hipStream_t)stream;
+  XS_HIP(s ? hipStreamSynchronize(s) : hipDeviceSynchronize());
+  std::vector<ReqDev> rd(count);
+  std::vector<unsigned long long> st(2 * (size_t)count + 1);
+  XS_HIP(hipMemcpy(rd.data(), d_ws, sizeof(ReqDev) * (size_t)count,
+                   hipMemcpyDeviceToHost));
+  XS_HIP(hipMemcpy(st.data(),
+                   (const char*)d_ws + align256b(sizeof(ReqDev) * (size_t)count),
+                   8 * st.size(), hipMemcpyDeviceToHost));
+  int dev = 0, khz = 0;
+  XS_HIP(hipGetDevice(&dev));
+  XS_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  const double us_per_tick = 1000.0 / (khz > 0 ? khz : 100000);
+  const unsigned long long t0 = st[2 * (size_t)count];
+  unsigned long long tmax = t0;
+  for (int i = 0; i < count; ++i)
+    if (st[2 * i] != ~0ull) tmax = std::max(tmax, st[2 * i + 1]);
+  if (makespan_us) *makespan_us = t0 == ~0ull ? 0.0 : (tmax - t0) * us_per_tick;
+  if (stats) {
+    for (int i = 0; i < count; ++i) {
+      xs_request_stats& r = stats[i];
+      r.n = rd[i].n;
+      if (st[2 * i] == ~0ull) {
+        r.start_us = r.end_us = r.latency_us = 0.0;
+        continue;
+      }
+      r.start_us = (st[2 * i] - t0) * us_per_tick;
+      r.end_us = (st[2 * i + 1] - t0) * us_per_tick;
+      r.latency_us = r.end_us - r.start_us;
+    }
+  }
   return XS_OK;
 }
 

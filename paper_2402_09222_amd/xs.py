@@ -226,6 +226,11 @@ def load_library(path: str = LIB_PATH):
         "xs_stream_wait": ([vp, P(xs_request_stats), P(ctypes.c_double)], i32),
         "xs_stream_params": ([vp, P(xs_params)], i32),
         "xs_stream_destroy": ([vp], i32),
+        "xs_lookup_requests": ([vp, P(xs_request), i32, P(xs_params), vp, sz, vp],
+                               i32),
+        "xs_requests_workspace_size": ([i32, P(sz)], i32),
+        "xs_requests_stats": ([vp, i32, vp, P(xs_request_stats),
+                               P(ctypes.c_double)], i32),
         "xs_status_string": ([i32], ctypes.c_char_p),
         "xs_last_error": ([], ctypes.c_char_p),
     }
@@ -609,3 +614,54 @@ def xs_stream_params(stream: Stream) -> xs_params:
 
 def xs_stream_destroy(stream: Stream):
     stream.close()
+
+
+class RequestBatch:
+    """Workspace and descriptors of one xs_lookup_requests call."""
+
+    def __init__(self, count: int, device):
+        b = ctypes.c_size_t()
+        _check(load_library().xs_requests_workspace_size(count, ctypes.byref(b)),
+               "xs_requests_workspace_size")
+        self.keep, self.ptr, self.nbytes = _workspace(b.value, device)
+        self.count = count
+        self.requests = None
+
+
+def xs_lookup_requests(tables: Tables, requests, params: xs_params = None,
+                       batch: RequestBatch = None, stream=None) -> RequestBatch:
+    """requests: list of (E, mat, out) device tensors.  Returns the batch
+    object (pass it to xs_requests_stats)."""
+    if not requests:
+        raise ValueError("no requests")
+    dev = requests[0][0].device
+    if batch is None or batch.count < len(requests):
+        batch = RequestBatch(len(requests), dev)
+    arr = (xs_request * len(requests))()
+    for i, (E, mat, out) in enumerate(requests):
+        _check_queries(E, mat)
+        if out.shape[0] < E.numel() or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [n, 5] tensor")
+        arr[i] = xs_request(E.numel(), E.data_ptr(), mat.data_ptr(),
+                            out.data_ptr())
+    batch.requests = list(requests)
+    batch.n_req = len(requests)
+    _check(load_library().xs_lookup_requests(
+        tables.handle, arr, len(requests),
+        ctypes.byref(params) if params is not None else None, batch.ptr,
+        batch.nbytes, _stream_ptr(stream, dev)), "xs_lookup_requests")
+    return batch
+
+
+def xs_requests_stats(batch: RequestBatch, stream=None):
+    """Synchronises and returns (stats list of dicts, makespan_us)."""
+    n = batch.n_req
+    stats = (xs_request_stats * n)()
+    mk = ctypes.c_double()
+    dev = batch.requests[0][0].device
+    _check(load_library().xs_requests_stats(batch.ptr, n,
+                                            _stream_ptr(stream, dev), stats,
+                                            ctypes.byref(mk)),
+           "xs_requests_stats")
+    return [dict(n=s.n, start_us=s.start_us, end_us=s.end_us,
+                 latency_us=s.latency_us) for s in stats], mk.value
