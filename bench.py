@@ -57,21 +57,32 @@ def lookup_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kind: str, n: int):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or
-    None when absent or taken on a different kernel source."""
+def kernel_name(p) -> str:
+    """The lookup kernel a resolved parameter set launches, as rocprofv3
+    names it (template arguments: grid, precision[, LPT, U])."""
+    if p.lds_stage:
+        return f"k_lookup_lds<{p.grid}, {p.precision}>"
+    return (f"k_lookup<{p.grid}, {p.precision}, {p.lookups_per_thread}, "
+            f"{p.unroll}>")
+
+
+def measured_traffic(kernel: str, block: int, n: int):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none for this kernel, block size and
+    batch, or it was taken on a different kernel source."""
     path = os.path.join(ROOT, "profiles", "lookup_traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(kind)
-    except (OSError, ValueError):
+        entries = json.load(open(path)).get("entries", [])
+    except (OSError, ValueError, AttributeError):
         return None
-    if not rec or rec.get("source_hash") != lookup_sources_hash():
-        return None
-    if rec.get("n_lookups") != n:
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    for rec in entries:
+        if (rec.get("kernel") == kernel and rec.get("block_size") == block
+                and rec.get("n_lookups") == n
+                and rec.get("source_hash") == lookup_sources_hash()):
+            return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def time_steps(fn, steps: int, warmup: int):
@@ -185,8 +196,12 @@ def sweep_in_flight(args, torch, synth, xs):
 def request_stream(args, torch, synth, xs):
     """Config 5: an uneven stream of requests (sizes log-uniform in
     [1e3, 1e6], energies 70 % log-uniform and 30 % from narrow peaks) served
-    by one persistent graph-launched kernel, against one xs_lookup_batch
-    launch per request with parameters tuned per size class."""
+    by one xs_lookup_requests call over the whole batch (batch-sorted: one
+    gathered, sorted queue; tile-sorted: one launch, tiles sorted in LDS),
+    against one xs_lookup_batch launch per request with parameters tuned per
+    size class.  A request's latency in the one-call forms runs from its
+    first tile's start to its last tile's end (device wall clock); per
+    launch it is the HIP event time of its call."""
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
              xs.XS_BUILD_UNION_BY_MATERIAL)
@@ -201,7 +216,7 @@ def request_stream(args, torch, synth, xs):
     log(f"{len(sizes)} requests, {total} lookups")
 
     # Tune the FP32 form per size class (10^3 .. 10^6) on slices of the stream.
-    for n in (1_000, 10_000, 100_000, 1_000_000):
+    for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
         cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
                                         max_evals=args.tune_evals, reps=3)
         r = xs.xs_tune(h, E[:n], m[:n], cfg)
@@ -230,26 +245,242 @@ def request_stream(args, torch, synth, xs):
         if rep > 0 and (best_launch is None or wall < best_launch["wall_s"]):
             best_launch = {"wall_s": wall, "lookups_per_s": total / wall,
                            "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
-    # One persistent kernel per batch of requests.
-    p_stream = xs.xs_resolve_params(h, 1_000_000, p_auto)
-    s = xs.xs_stream_create(h, p_stream, max_requests=len(reqs))
-    best_stream = None
-    for rep in range(max(1, args.steps // 5) + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xs.xs_stream_submit(s, reqs)
-        stats, makespan = xs.xs_stream_wait(s)
-        wall = time.perf_counter() - t0
-        lat = [r["latency_us"] for r in stats]
-        if rep > 0 and (best_stream is None or wall < best_stream["wall_s"]):
-            best_stream = {"wall_s": wall, "lookups_per_s": total / wall,
-                           "device_makespan_us": makespan,
-                           "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
-    s.close()
+    # The whole batch in one call: batch-sorted (automatic parameters, a
+    # sort policy) and tile-sorted (no global sort).
+    def one_call(params):
+        batch = None
+        best = None
+        for rep in range(max(1, args.steps // 5) + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            batch = xs.xs_lookup_requests(h, reqs, params=params, batch=batch)
+            stats, makespan = xs.xs_requests_stats(batch)
+            wall = time.perf_counter() - t0
+            lat = [r["latency_us"] for r in stats]
+            if rep > 0 and (best is None or wall < best["wall_s"]):
+                best = {"wall_s": wall, "lookups_per_s": total / wall,
+                        "device_makespan_us": makespan,
+                        "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
+        return best
+
+    p_batch = xs.xs_resolve_params(h, total, p_auto)
+    p_tile = xs.xs_params_default(xs.XS_FP32)
+    p_tile.sort = xs.XS_SORT_NONE
+    p_tile = xs.xs_resolve_params(h, total, p_tile)
+    res_batch = one_call(p_batch)
+    res_tile = one_call(p_tile)
     print(json.dumps({"config": "uneven request stream", "requests": len(reqs),
                       "lookups": total, "per_request_launches": best_launch,
-                      "persistent_graph_kernel": best_stream,
-                      "stream_params": p_stream.as_dict()}), flush=True)
+                      "one_call_batch_sorted": res_batch,
+                      "one_call_tile_sorted": res_tile,
+                      "batch_params": p_batch.as_dict(),
+                      "tile_params": p_tile.as_dict()}), flush=True)
+    h.close()
+    return 0
+
+
+def tuner_study(args, torch, synth, xs):
+    """The paper's search against exhaustive search on the tuning space
+    (grid method x sort x block x lookups/lane x nuclides in flight x LDS
+    staging, FP32 form) for one batch of the full-size workload.  Every
+    configuration is timed once (best of 3 after 1 warm-up, HIP events);
+    then the forest search (LCB, kappa 1.96) and uniform random search are
+    replayed on that measured table over many seeds, so both see identical
+    costs.  Reports how close each gets to the optimum and after how many
+    evaluations it first lands within 5 % of it."""
+    t = synth.config2_tables()
+    n = args.study_n
+    q = synth.config4_queries(5, n) if n <= 8_000_000 else synth.config2_queries(n)
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    h = xs.xs_create_tables(t, flags, args.bins)
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    out = torch.empty((n, 5), device="cuda:0", dtype=torch.float32)
+    ws = xs._workspace(xs.xs_workspace_size(h, n, xs.make_params(
+        xs.XS_FP32, sort="band_material", sort_threshold=0)), E.device)
+    st = torch.cuda.current_stream()
+    ev = (torch.cuda.Event(enable_timing=True),
+          torch.cuda.Event(enable_timing=True))
+    keyf = ("grid", "sort", "block_size", "lookups_per_thread", "unroll",
+            "lds_stage")
+    table = {}
+
+    def measure(p, cutoff):
+        k = tuple(getattr(p, f) for f in keyf)
+        xs.xs_lookup_batch(h, E, m, out=out, params=p, workspace=ws)
+        best = float("inf")
+        for _ in range(3):
+            ev[0].record(st)
+            xs.xs_lookup_batch(h, E, m, out=out, params=p, workspace=ws)
+            ev[1].record(st)
+            ev[1].synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]))
+        table[k] = best
+        return best
+
+    log(f"tuner study: exhaustive timing of the space at n={n}")
+    t0 = time.perf_counter()
+    ex = xs.xs_tune_search(7, xs.xs_tune_config_default(
+        precision=xs.XS_FP32, strategy=xs.XS_TUNE_EXHAUSTIVE,
+        timeout_factor=0.0), measure)
+    wall = time.perf_counter() - t0
+    opt = ex.best_ms
+    log(f"exhaustive: {ex.space_size} configurations in {wall:.1f} s, "
+        f"optimum {opt:.3f} ms {ex.best.as_dict()}")
+
+    def replay(p, cutoff):
+        return table[tuple(getattr(p, f) for f in keyf)]
+
+    evals = args.tune_evals
+    forest = []
+    for seed in range(args.study_seeds):
+        trace = []
+
+        def rec(p, cutoff):
+            v = replay(p, cutoff)
+            trace.append(v)
+            return v
+        r = xs.xs_tune_search(7, xs.xs_tune_config_default(
+            precision=xs.XS_FP32, strategy=xs.XS_TUNE_FOREST,
+            max_evals=evals, seed=seed), rec)
+        run_best = np.minimum.accumulate(trace)
+        hit = np.nonzero(run_best <= 1.05 * opt)[0]
+        forest.append((r.best_ms / opt, int(hit[0]) + 1 if len(hit) else None))
+    costs = np.array(sorted(table.values()))
+    rng = np.random.default_rng(7)
+    rand = []
+    allv = np.array(list(table.values()))
+    for seed in range(args.study_seeds):
+        pick = allv[rng.choice(len(allv), evals, replace=False)]
+        run_best = np.minimum.accumulate(pick)
+        hit = np.nonzero(run_best <= 1.05 * opt)[0]
+        rand.append((run_best[-1] / opt, int(hit[0]) + 1 if len(hit) else None))
+
+    def summary(rows):
+        ratio = [r for r, _ in rows]
+        hits = [e for _, e in rows if e is not None]
+        return {"mean_best_over_opt": float(np.mean(ratio)),
+                "max_best_over_opt": float(np.max(ratio)),
+                "runs_within_5pct": len(hits),
+                "median_evals_to_5pct": (float(np.median(hits)) if hits
+                                         else None)}
+    line = {"study": "tuner", "n_lookups": n, "space_size": ex.space_size,
+            "evals_per_search": evals, "seeds": args.study_seeds,
+            "exhaustive": {"best_ms": opt, "best": ex.best.as_dict(),
+                           "wall_s": wall,
+                           "configs_within_5pct": int(np.sum(costs <= 1.05 * opt)),
+                           "median_ms": float(np.median(costs))},
+            "forest_lcb": summary(forest), "random": summary(rand)}
+    print(json.dumps(line), flush=True)
+    h.close()
+    return 0
+
+
+def energy_study(args, torch, synth, xs):
+    """Run time, energy and energy-delay product of the full-size lookup
+    (the paper's three objectives, section 7).  The FP32 form is tuned three
+    times with the forest search, once per objective, each evaluation
+    running the batch for >= 0.15 s between two readings of the board's
+    energy accumulator; the three winners and the plain FP64 form are then
+    measured over >= 1 s each."""
+    from paper_2402_09222_amd.energy import EnergyMeter, measure
+    meter = EnergyMeter(0)
+    t = synth.config2_tables()
+    q = synth.config2_queries(args.n)
+    n = len(q)
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    h = xs.xs_create_tables(t, flags, args.bins)
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    outs = {0: torch.empty((n, 5), device="cuda:0", dtype=torch.float64),
+            1: torch.empty((n, 5), device="cuda:0", dtype=torch.float32)}
+    ws = xs._workspace(xs.xs_workspace_size(h, n, xs.make_params(
+        xs.XS_FP32, sort="band_material", sort_threshold=0)), E.device)
+
+    def call(p):
+        return lambda: xs.xs_lookup_batch(h, E, m, out=outs[p.precision],
+                                          params=p, workspace=ws)
+
+    objective = {"time_ms": lambda s, j: s * 1e3,
+                 "energy_j": lambda s, j: j,
+                 "edp_js": lambda s, j: j * s}
+    winners = {}
+    for name, f in objective.items():
+        log(f"energy study: tuning for {name}")
+
+        def evaluate(p, cutoff, f=f):
+            sec, joule = measure(call(p), meter, min_seconds=0.15)
+            return f(sec, joule)
+        r = xs.xs_tune_search(7, xs.xs_tune_config_default(
+            precision=xs.XS_FP32, strategy=xs.XS_TUNE_FOREST,
+            max_evals=args.tune_evals, seed=1), evaluate)
+        winners[name] = r.best
+    plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
+                           block_size=256, lookups_per_thread=1, unroll=1,
+                           lds_stage=0, sort_threshold=xs.INT64_MAX)
+    rows = {}
+    for label, p in [("plain_fp64", plain)] + [(f"fp32_best_{k}", v)
+                                               for k, v in winners.items()]:
+        p = xs.xs_resolve_params(h, n, p)
+        sec, joule = measure(call(p), meter, min_seconds=1.0)
+        rows[label] = {"params": p.as_dict(), "ms": sec * 1e3,
+                       "joules": joule, "watts": joule / sec,
+                       "nj_per_lookup": joule / n * 1e9,
+                       "edp_js": joule * sec,
+                       "lookups_per_s": n / sec}
+        log(f"{label}: {sec*1e3:.3f} ms, {joule:.4f} J, {joule/sec:.0f} W")
+    print(json.dumps({"study": "energy", "n_lookups": n, "forms": rows}),
+          flush=True)
+    meter.close()
+    h.close()
+    return 0
+
+
+def stream_study(args, torch, synth, xs):
+    """One batch split over k concurrent streams sharing one table handle
+    (the paper's several MPI ranks per GPU, section 5.1) against one launch
+    of the whole batch with the same parameters.  Each stream gets a
+    contiguous share of the 10M lookups, its own workspace and output, and
+    its own sort; the time is the wall time of the whole batch."""
+    t = synth.config2_tables()
+    q = synth.config2_queries(args.n)
+    n = len(q)
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    h = xs.xs_create_tables(t, flags, args.bins)
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    out = torch.empty((n, 5), device="cuda:0", dtype=torch.float32)
+    cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
+                                    max_evals=args.tune_evals, reps=3)
+    xs.xs_tune(h, E, m, cfg)
+    rows = []
+    for k in (1, 2, 4, 8):
+        parts = [(i * n // k, (i + 1) * n // k) for i in range(k)]
+        p = xs.xs_resolve_params(h, parts[0][1] - parts[0][0],
+                                 xs.xs_params_default(xs.XS_FP32))
+        streams = [torch.cuda.Stream() for _ in range(k)]
+        wss = [xs._workspace(xs.xs_workspace_size(h, b - a, p), E.device)
+               for a, b in parts]
+
+        def step():
+            cur = torch.cuda.current_stream()
+            for s in streams:
+                s.wait_stream(cur)
+            for s, (a, b), w in zip(streams, parts, wss):
+                with torch.cuda.stream(s):
+                    xs.xs_lookup_batch(h, E[a:b], m[a:b], out=out[a:b],
+                                       params=p, workspace=w, stream=s)
+            for s in streams:
+                cur.wait_stream(s)
+        sec = time_steps(step, args.steps, args.warmup)
+        rows.append({"streams": k, "params": p.as_dict(), "ms": sec * 1e3,
+                     "lookups_per_s": n / sec})
+        log(f"{k} streams: {sec*1e3:.3f} ms, {n/sec:.4g} lookups/s")
+    print(json.dumps({"study": "concurrent streams", "n_lookups": n,
+                      "rows": rows}), flush=True)
     h.close()
     return 0
 
@@ -277,6 +508,16 @@ def main(argv=None):
                     help="2: the headline line (default); 4: particles-in-"
                          "flight sweep; 5: uneven request stream")
     ap.add_argument("--stream-requests", type=int, default=2000)
+    ap.add_argument("--tuner-study", action="store_true",
+                    help="exhaustive vs forest vs random search on the "
+                         "tuning space (evaluations to the optimum)")
+    ap.add_argument("--study-n", type=int, default=4_000_000)
+    ap.add_argument("--study-seeds", type=int, default=20)
+    ap.add_argument("--streams", action="store_true",
+                    help="one batch split over 1, 2, 4, 8 concurrent streams")
+    ap.add_argument("--energy", action="store_true",
+                    help="run time / energy / EDP of the lookup and tuning "
+                         "for each objective (board energy accumulator)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 GiB and exit (the "
                          "achievable-bandwidth figure and the reference for "
@@ -304,6 +545,12 @@ def main(argv=None):
               flush=True)
         return 0
 
+    if args.streams:
+        return stream_study(args, torch, synth, xs)
+    if args.energy:
+        return energy_study(args, torch, synth, xs)
+    if args.tuner_study:
+        return tuner_study(args, torch, synth, xs)
     if args.config == 4:
         return sweep_in_flight(args, torch, synth, xs)
     if args.config == 5:
@@ -336,13 +583,15 @@ def main(argv=None):
             xs.xs_lookup_batch(h, E, m, out=out, params=params, workspace=ws)
         return fn
 
-    def measure(params, kind):
+    def measure(params):
+        params = xs.xs_resolve_params(h, n, params)
         fn = runner(params)
         sec = time_steps(fn, args.steps, args.warmup)
         kt = kernel_time(xs, h, fn, max(args.steps, 3))
         B = bytes_per_lookup(params.precision, nbar)
         achieved = n * B / (kt["ms_lookup"] * 1e-3) / 1e9
-        traffic = measured_traffic(kind, n)
+        kname = kernel_name(params)
+        traffic = measured_traffic(kname, params.block_size, n)
         return {
             "value": n / sec, "ms_per_step": sec * 1e3,
             "params": params.as_dict(), "kernel_ms": kt,
@@ -350,6 +599,8 @@ def main(argv=None):
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic,
+                         "kernel": kname,
+                         "kernel_ms": kt["ms_lookup"],
                          "bytes_per_lookup": B},
         }
 
@@ -357,10 +608,11 @@ def main(argv=None):
     if args.only in (None, "plain"):
         p_plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
                                  block_size=256, lookups_per_thread=1,
-                                 lds_stage=0, sort_threshold=xs.INT64_MAX,
+                                 unroll=1, lds_stage=0,
+                                 sort_threshold=xs.INT64_MAX,
                                  queue=xs.XS_QUEUE_COMPACT)
         log("timing plain FP64")
-        plain = measure(p_plain, "plain_fp64")
+        plain = measure(p_plain)
         log(f"plain FP64: {plain['value']:.4g} lookups/s, "
             f"{plain['ms_per_step']:.3f} ms/step")
     tune_report = None
@@ -386,7 +638,7 @@ def main(argv=None):
             # caller passing automatic parameters would
             p32 = xs.xs_resolve_params(h, n, xs.xs_params_default(xs.XS_FP32))
         log("timing FP32 form with", p32.as_dict())
-        tuned = measure(p32, "tuned_fp32")
+        tuned = measure(p32)
         tuned["tuner"] = tune_report
         log(f"FP32 tuned: {tuned['value']:.4g} lookups/s, "
             f"{tuned['ms_per_step']:.3f} ms/step")

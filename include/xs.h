@@ -373,19 +373,35 @@ xs_status xs_stream_params(xs_stream_t s, xs_params* out);
 /* Waits for any batch in flight and frees the stream.  NULL is a no-op. */
 xs_status xs_stream_destroy(xs_stream_t s);
 
-/* One launch for a batch of requests (HOST array of count descriptors, read
- * during the call): the grid has one 256-lane block per 1024-lookup tile of
- * the batch; each block sorts its tile in LDS by material and energy, looks
- * it up and stamps the request's first and last tile with the device wall
- * clock.  params as for xs_stream_create.  d_ws: DEVICE, 256-byte aligned, at
- * least xs_requests_workspace_size(count) bytes; it holds the descriptors and
- * stamps until xs_requests_stats reads them.  Results equal xs_lookup_batch's
- * bit for bit. */
+/* A batch of requests served together (HOST array of count descriptors,
+ * read during the call); the paper's queue of particles in flight (section
+ * 5.1) fed by many callers at once.  Parameters are resolved as for one
+ * batch of the total size (NULL = tuned defaults), and the sort policy picks
+ * the mode:
+ *  - sort != XS_SORT_NONE and total >= sort_threshold (batch-sorted): one
+ *    gather kernel copies every request into one queue, the queue is sorted
+ *    and looked up as in xs_lookup_batch, and one scatter kernel writes each
+ *    request's results back; a request's time runs from its first gathered
+ *    tile to its last scattered tile;
+ *  - otherwise (tile-sorted): one launch with a 256-lane block per
+ *    1024-lookup tile of each request; the block sorts its tile in LDS by
+ *    material and energy and looks it up; a request's time runs from its
+ *    first tile's start to its last tile's end.
+ * Times come from the device wall clock.  d_ws: DEVICE, 256-byte aligned,
+ * at least xs_requests_workspace_size(...) bytes for the same requests and
+ * params; it holds the descriptors and times until xs_requests_stats reads
+ * them.  Results equal xs_lookup_batch's on each request bit for bit.
+ * Errors: XS_EINVAL (count outside [1, 2^24], a request with n < 0 or
+ * n >= 2^31, NULL pointers in a non-empty request, a total of 2^31 lookups
+ * or more), XS_EWORKSPACE, XS_ENOTBUILT (grid or precision not built). */
 xs_status xs_lookup_requests(xs_tables_t tables, const xs_request* reqs,
                              int32_t count, const xs_params* params,
                              void* d_ws, size_t ws_bytes, void* stream);
 
-xs_status xs_requests_workspace_size(int32_t count, size_t* bytes);
+/* Workspace bytes xs_lookup_requests needs for these requests and params. */
+xs_status xs_requests_workspace_size(xs_tables_t tables, const xs_request* reqs,
+                                     int32_t count, const xs_params* params,
+                                     size_t* bytes);
 
 /* Synchronises `stream` and reads the per-request times of the last
  * xs_lookup_requests call that used d_ws (stats[count] may be NULL). */

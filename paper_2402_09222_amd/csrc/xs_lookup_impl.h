@@ -154,7 +154,11 @@ struct Locator<XS_GRID_UNIONIZED> {
   const int32_t* urow;
   int jbase;  // first list position of the material (by-material layout)
   __device__ __forceinline__ void init(const DevTables& t, double e, int m) {
-    const int64_t j = bisect_le(t.u, (int)t.U, e);
+    init_row(t, bisect_le(t.u, (int)t.U, e), m);
+  }
+  // State for union point j (the bracket of E in the union grid).
+  __device__ __forceinline__ void init_row(const DevTables& t, int64_t j,
+                                           int m) {
     if (t.union_by_material) {
       jbase = t.moff[m];
       const int64_t L = t.moff[m + 1] - jbase;
@@ -548,21 +552,31 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 // ---- LDS-staged lookup -------------------------------------------------------------
 //
 // For a block whose lookups all share one material (the usual case after a
-// sort), each nuclide's brackets lie between those of the block's lowest and
-// highest energies.  Two lanes find those two brackets, the block loads the
-// records in between into LDS with one cooperative read, and every lane
-// bisects and interpolates from LDS.  A window wider than kStageCap records,
-// or a block holding several materials, takes the per-lane path.  Same
-// arithmetic, same order: the sums are bit-identical to k_lookup's.
+// sort), each nuclide's bracket lies between the brackets of the block's
+// lowest and highest energies.  The material's nuclides are taken in groups
+// of kLdsGroup: lane i of the block finds the window of nuclide i of the
+// group (from the lower edge's bracket to the upper edge's bracket + 1), the
+// block copies every window of at most kLdsW records into LDS with one
+// cooperative read, and each lane then walks the group's nuclides in list
+// order, bisecting its window in LDS and interpolating from it.  A nuclide
+// whose window is wider takes the per-lane search for that nuclide; a block
+// holding several materials (or a partial last block) takes the per-lane
+// walk.  Same arithmetic, same order: the sums are bit-identical to
+// k_lookup's.  Three barriers per group of nuclides instead of a search and
+// a window load per (lookup, nuclide).
 
-constexpr int kStageCap = 64;
+constexpr int kLdsW = 8;       // records per staged window
+constexpr int kLdsGroup = 32;  // nuclides per staging round
 
 template <int GRID, int PREC>
 __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
                                                      const LookupArgs a) {
   using R = typename RecOf<PREC>::T;
-  __shared__ R stage[kStageCap];
-  __shared__ int s_mat, s_win[2];
+  __shared__ R stage[kLdsGroup * kLdsW];
+  __shared__ int s_first[kLdsGroup];  // first staged record, or -1: per lane
+  __shared__ int s_width[kLdsGroup];  // records in the window
+  __shared__ int s_mat;
+  __shared__ int64_t s_row[2];
   __shared__ double s_red[2][16];
   const int tid = threadIdx.x;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -591,15 +605,12 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
   const int mb = s_mat;
   const bool uniform = __syncthreads_and(act && m == mb && mb >= 0);
 
-  Locator<GRID> loc;
-  Acc<PREC> acc;
-  loc.init(t, e, m);
-  acc.zero();
   if (!uniform) {
     if (act) {
       const double e1[1] = {e};
-      Locator<GRID> l1[1] = {loc};
+      Locator<GRID> l1[1];
       Acc<PREC> a1[1];
+      l1[0].init(t, e, m);
       a1[0].zero();
       walk_material<GRID, PREC, 1, 1>(t, m, e1, l1, a1);
       a1[0].store(a.out, o);
@@ -626,37 +637,71 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
     lo_e = fmin(lo_e, s_red[0][i]);
     hi_e = fmax(hi_e, s_red[1][i]);
   }
-  Locator<GRID> edge = loc;  // lanes 0 and 1: the block's lowest / highest E
-  if (tid < 2) edge.init(t, tid == 0 ? lo_e : hi_e, mb);
 
+  // Search state of the two edge energies: the union grid is bisected once
+  // by two lanes; the hash bin is arithmetic; bisection keeps no state.
+  Locator<GRID> edge_lo, edge_hi;
+  if constexpr (GRID == XS_GRID_UNIONIZED) {
+    if (tid < 2) s_row[tid] = bisect_le(t.u, (int)t.U, tid == 0 ? lo_e : hi_e);
+    __syncthreads();
+    edge_lo.init_row(t, s_row[0], mb);
+    edge_hi.init_row(t, s_row[1], mb);
+  } else {
+    edge_lo.init(t, lo_e, mb);
+    edge_hi.init(t, hi_e, mb);
+  }
+
+  Locator<GRID> loc;  // this lane's own search state, made on first need
+  bool have_loc = false;
+  Acc<PREC> acc;
+  acc.zero();
   const R* recs = RecOf<PREC>::base(t);
   const int j0 = ld_const(t.moff + mb), j1 = ld_const(t.moff + mb + 1);
-  for (int j = j0; j < j1; ++j) {
-    const MatRec r = ld_const(t.mrec + j);
-    if (tid < 2) s_win[tid] = exact_bracket(t, edge, r, j, tid == 0 ? lo_e : hi_e);
-    __syncthreads();
-    const int ilo = s_win[0], width = s_win[1] - ilo + 2;
-    const auto rho = Acc<PREC>::rho(t, r, j);
-    if (width <= kStageCap) {
-      if (tid < width) stage[tid] = recs[r.base + ilo + tid];
-      __syncthreads();
-      // largest p in [0, width-2] with stage[p].e <= e, else 0
-      int p = 0, len = width - 1;
-      while (len > 1) {
-        const int half = len >> 1;
-        p = (stage[p + half].e <= e) ? p + half : p;
-        len -= half;
-      }
-      acc.add(stage[p], stage[p + 1], e, rho);
-    } else {
-      const int cand = loc.start(t, r, j, e);
-      Window<GRID, PREC> win;
-      win.load(t, r, cand);
-      R lo, hi;
-      win.finish(t, r, loc, cand, e, lo, hi);
-      acc.add(lo, hi, e, rho);
+  for (int jg = j0; jg < j1; jg += kLdsGroup) {
+    const int cnt = min(kLdsGroup, j1 - jg);
+    if (tid < cnt) {
+      const MatRec r = t.mrec[jg + tid];
+      const int lo = exact_bracket(t, edge_lo, r, jg + tid, lo_e);
+      const int hi = exact_bracket(t, edge_hi, r, jg + tid, hi_e);
+      const int width = hi - lo + 2;  // grid points lo .. hi + 1
+      s_first[tid] = width <= kLdsW ? r.base + lo : -1;
+      s_width[tid] = width;
     }
-    __syncthreads();  // stage and s_win are rewritten for the next nuclide
+    __syncthreads();
+    for (int s = tid; s < cnt * kLdsW; s += blockDim.x) {
+      const int i = s / kLdsW, k = s % kLdsW;
+      const int first = s_first[i];
+      if (first >= 0 && k < s_width[i]) stage[s] = recs[first + k];
+    }
+    __syncthreads();
+    for (int i = 0; i < cnt; ++i) {
+      const int j = jg + i;
+      const MatRec r = ld_const(t.mrec + j);
+      const auto rho = Acc<PREC>::rho(t, r, j);
+      if (s_first[i] >= 0) {
+        // largest p in [0, width-2] with win[p].e <= e, else 0
+        const R* win = stage + i * kLdsW;
+        int p = 0, len = s_width[i] - 1;
+        while (len > 1) {
+          const int half = len >> 1;
+          p = (win[p + half].e <= e) ? p + half : p;
+          len -= half;
+        }
+        acc.add(win[p], win[p + 1], e, rho);
+      } else {
+        if (!have_loc) {
+          loc.init(t, e, mb);
+          have_loc = true;
+        }
+        const int cand = loc.start(t, r, j, e);
+        Window<GRID, PREC> win;
+        win.load(t, r, cand);
+        R lo, hi;
+        win.finish(t, r, loc, cand, e, lo, hi);
+        acc.add(lo, hi, e, rho);
+      }
+    }
+    __syncthreads();  // the stage and window tables are rewritten next group
   }
   acc.store(a.out, o);
 }

@@ -139,7 +139,9 @@ __global__ __launch_bounds__(256) void k_row_scan(
 // Stable scatter of one digit pass.  Wave w of the block owns the tile's
 // elements [w*1024, (w+1)*1024), read 64 at a time in order, so the order
 // (wave, round, lane) is input order.  wcnt[w][d] counts digit d so far in
-// wave w; after the rounds the waves' counts are prefixed per digit.
+// wave w.  The tile is first reordered in LDS by digit (stable), then
+// written out in that order: consecutive lanes write consecutive positions
+// of one digit's run instead of 64 scattered words per wave.
 template <bool FROM_INPUT, bool WRITE_KEYS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     SortSrc src, const uint32_t* __restrict__ keys_in,
@@ -148,7 +150,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
   constexpr int kWaves = kSortThreads / 64;
   constexpr int kPerWave = kSortTile / kWaves;
+  static_assert(kSortThreads == kRadixBins, "one thread per digit");
   __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  __shared__ int32_t gdelta[kRadixBins];  // output position - tile position
+  __shared__ uint32_t skey[kSortTile];
+  __shared__ uint32_t sval[kSortTile];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int i = tid; i < kWaves * kRadixBins; i += kSortThreads)
     (&wcnt[0][0])[i] = 0;
@@ -156,7 +162,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __syncthreads();
 
   const uint64_t below = lanes_below(lane);
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + w * kPerWave;
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = tile0 + w * kPerWave;
   uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -189,13 +196,23 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
   __syncthreads();
   {
-    uint32_t s = tile_off;
+    // Thread tid owns digit tid: its waves' counts become their first tile
+    // positions, and the digit's tile start maps to its output start.
+    uint32_t c[kWaves], tot = 0;
 #pragma unroll
     for (int ww = 0; ww < kWaves; ++ww) {
-      const uint32_t c = wcnt[ww][tid];
-      wcnt[ww][tid] = s;
-      s += c;
+      c[ww] = wcnt[ww][tid];
+      tot += c[ww];
     }
+    uint32_t all;
+    const uint32_t start = block_incl_scan<kSortThreads>(tot, &all) - tot;
+    uint32_t s = start;
+#pragma unroll
+    for (int ww = 0; ww < kWaves; ++ww) {
+      wcnt[ww][tid] = s;
+      s += c[ww];
+    }
+    gdelta[tid] = (int32_t)(tile_off - start);
   }
   __syncthreads();
 #pragma unroll
@@ -203,11 +220,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int64_t i = base + r * 64 + lane;
     if (i < src.n) {
       const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
-      const uint32_t pos = wcnt[w][d] + rank[r];
-      if (pos < (uint64_t)src.n) {  // always true when offsets are consistent
-        if (WRITE_KEYS) keys_out[pos] = key[r];
-        vals_out[pos] = val[r];
-      }
+      const uint32_t lp = wcnt[w][d] + rank[r];
+      skey[lp] = key[r];
+      sval[lp] = val[r];
+    }
+  }
+  __syncthreads();
+  const int cnt = (int)min<int64_t>(kSortTile, src.n - tile0);
+  for (int j = tid; j < cnt; j += kSortThreads) {
+    const uint32_t k = skey[j];
+    const uint32_t d = (k >> shift) & (kRadixBins - 1);
+    const int64_t pos = (int64_t)j + gdelta[d];
+    if ((uint64_t)pos < (uint64_t)src.n) {  // always true with consistent offsets
+      if (WRITE_KEYS) keys_out[pos] = k;
+      vals_out[pos] = sval[j];
     }
   }
 }

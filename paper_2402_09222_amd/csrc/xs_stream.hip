@@ -33,6 +33,7 @@ struct ReqDev {
   void* out;
   int64_t n;
   int64_t tile_begin;  // first global tile of the request
+  int64_t begin;       // first position in the batch's concatenated order
 };
 
 struct StreamHeader {
@@ -221,6 +222,51 @@ __global__ void k_requests_init(unsigned long long* stamps, int count) {
   if (i == 0) stamps[2 * count] = ~0ull;
 }
 
+// Batch-sorted mode, step 1: block b copies tile b of its request into the
+// concatenated (E, material) arrays and stamps the request's start.
+__global__ __launch_bounds__(kStreamThreads) void k_requests_gather(
+    const ReqDev* __restrict__ reqs, int count, double* __restrict__ E_all,
+    int32_t* __restrict__ m_all, unsigned long long* stamps) {
+  const int64_t g = blockIdx.x;
+  const unsigned long long t0 = wall_clock64();
+  const int r = request_of(reqs, count, g);
+  const ReqDev R = reqs[r];
+  const int64_t base = (g - R.tile_begin) * kStreamTile;
+#pragma unroll
+  for (int p = 0; p < kPerLane; ++p) {
+    const int64_t q = base + threadIdx.x + p * kStreamThreads;
+    if (q < R.n) {
+      E_all[R.begin + q] = R.E[q];
+      m_all[R.begin + q] = R.mat[q];
+    }
+  }
+  if (threadIdx.x == 0) {
+    atomicMin(&stamps[2 * r], t0);
+    atomicMin(&stamps[2 * count], t0);
+  }
+}
+
+// Batch-sorted mode, step 3: block b copies tile b of its request's results
+// from the concatenated output and stamps the request's end.
+template <class T>
+__global__ __launch_bounds__(kStreamThreads) void k_requests_scatter(
+    const ReqDev* __restrict__ reqs, int count, const T* __restrict__ out_all,
+    unsigned long long* stamps) {
+  const int64_t g = blockIdx.x;
+  const int r = request_of(reqs, count, g);
+  const ReqDev R = reqs[r];
+  const int64_t base = (g - R.tile_begin) * kStreamTile * XS_CHANNELS;
+  const int64_t len = R.n * XS_CHANNELS;
+  T* out = (T*)R.out;
+  const T* src = out_all + R.begin * XS_CHANNELS;
+  for (int k = threadIdx.x; k < kStreamTile * XS_CHANNELS; k += kStreamThreads) {
+    const int64_t q = base + k;
+    if (q < len) out[q] = src[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&stamps[2 * r + 1], wall_clock64());
+}
+
 }  // namespace
 }  // namespace xs
 
@@ -402,7 +448,7 @@ xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
       return fail(XS_EINVAL, "request %d: n out of range", i);
     if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
       return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
-    rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles};
+    rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles, 0};
     tiles += (r.n + kStreamTile - 1) / kStreamTile;
     s->sizes[i] = r.n;
   }
@@ -522,16 +568,73 @@ void energy_key_shift(const xs_tables_s* h, int64_t* bmin, int* shift) {
   *shift = sh;
 }
 
+// Validation, parameters and workspace layout of one xs_lookup_requests call.
+struct RequestPlan {
+  xs_params p{};
+  int64_t total = 0;   // lookups in the batch
+  int64_t tiles = 0;   // 1024-lookup tiles (each request starts a tile)
+  bool batch_sorted = false;
+  size_t off_stamps = 0, off_E = 0, off_mat = 0, off_out = 0,
+         off_lookup_ws = 0, lookup_ws_bytes = 0, ws_bytes = 0;
+};
+
+xs_status plan_requests(xs_tables_t h, const xs_request* reqs, int32_t count,
+                        const xs_params* params, RequestPlan* plan) {
+  if (!h) return fail(XS_EINVAL, "table handle is NULL");
+  if (count < 1 || count > (1 << 24) || !reqs)
+    return fail(XS_EINVAL, "count must be in [1, 2^24] and reqs not NULL");
+  RequestPlan q;
+  for (int i = 0; i < count; ++i) {
+    const xs_request& r = reqs[i];
+    if (r.n < 0 || r.n > 0x7fffffffLL)
+      return fail(XS_EINVAL, "request %d: n out of range", i);
+    if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
+      return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
+    q.total += r.n;
+    q.tiles += (r.n + kStreamTile - 1) / kStreamTile;
+  }
+  if (q.tiles > 0x7fffffffLL || q.total > 0x7fffffffLL)
+    return fail(XS_EINVAL, "batch too large (at most 2^31 - 1 lookups)");
+  // Parameters as for one batch of the whole size.
+  if (xs_status st = xs_resolve_params(h, std::max<int64_t>(q.total, 1), params,
+                                       &q.p))
+    return st;
+  q.batch_sorted = q.p.sort != XS_SORT_NONE && q.total >= q.p.sort_threshold &&
+                   q.total > 0;
+  size_t off = align256b(sizeof(ReqDev) * (size_t)count);
+  q.off_stamps = off;
+  off += align256b(8 * (2 * (size_t)count + 1));
+  if (q.batch_sorted) {
+    const size_t esz = q.p.precision == XS_FP64 ? 8 : 4;
+    q.off_E = off;
+    off += align256b(8 * (size_t)q.total);
+    q.off_mat = off;
+    off += align256b(4 * (size_t)q.total);
+    q.off_out = off;
+    off += align256b(esz * XS_CHANNELS * (size_t)q.total);
+    if (xs_status st = xs_workspace_size(h, q.total, &q.p, &q.lookup_ws_bytes))
+      return st;
+    q.off_lookup_ws = off;
+    off += align256b(q.lookup_ws_bytes);
+  }
+  q.ws_bytes = off;
+  *plan = q;
+  return XS_OK;
+}
+
 }  // namespace
 }  // namespace xs
 
 extern "C" {
 
-xs_status xs_requests_workspace_size(int32_t count, size_t* bytes) {
+xs_status xs_requests_workspace_size(xs_tables_t h, const xs_request* reqs,
+                                     int32_t count, const xs_params* params,
+                                     size_t* bytes) {
   clear_error();
-  if (!bytes || count < 1) return fail(XS_EINVAL, "count >= 1 and bytes needed");
-  *bytes = align256b(sizeof(ReqDev) * (size_t)count) +
-           align256b(8 * (2 * (size_t)count + 1));
+  if (!bytes) return fail(XS_EINVAL, "bytes is NULL");
+  RequestPlan plan;
+  if (xs_status st = plan_requests(h, reqs, count, params, &plan)) return st;
+  *bytes = plan.ws_bytes;
   return XS_OK;
 }
 
@@ -539,26 +642,20 @@ xs_status xs_lookup_requests(xs_tables_t h, const xs_request* reqs,
                              int32_t count, const xs_params* params,
                              void* d_ws, size_t ws_bytes, void* stream) {
   clear_error();
-  if (!h) return fail(XS_EINVAL, "table handle is NULL");
-  if (count < 1 || count > (1 << 24) || !reqs)
-    return fail(XS_EINVAL, "count must be in [1, 2^24] and reqs not NULL");
-  xs_params p;
-  if (xs_status st = xs_resolve_params(h, 1 << 20, params, &p)) return st;
-  size_t need = 0;
-  xs_requests_workspace_size(count, &need);
-  if (!d_ws || ws_bytes < need || (uintptr_t)d_ws % 256)
+  RequestPlan plan;
+  if (xs_status st = plan_requests(h, reqs, count, params, &plan)) return st;
+  if (!d_ws || ws_bytes < plan.ws_bytes || (uintptr_t)d_ws % 256)
     return fail(XS_EWORKSPACE, "a 256-byte aligned workspace of %zu bytes is "
-                "needed", need);
+                "needed", plan.ws_bytes);
   int dev = -1;
   XS_HIP(hipGetDevice(&dev));
   if (dev != h->device)
     return fail(XS_EINVAL, "current device %d is not the tables' device %d",
                 dev, h->device);
   hipStream_t s = (hipStream_t)stream;
-  ReqDev* reqs_dev = (ReqDev*)d_ws;
-  auto* stamps = (unsigned long long*)((char*)d_ws +
-                                      align256b(sizeof(ReqDev) * (size_t)count));
-  int64_t tiles = 0;
+  char* ws = (char*)d_ws;
+  ReqDev* reqs_dev = (ReqDev*)ws;
+  auto* stamps = (unsigned long long*)(ws + plan.off_stamps);
   {
     std::lock_guard<std::mutex> lk(h->mu);
     const size_t bytes = sizeof(ReqDev) * (size_t)count;
@@ -573,36 +670,59 @@ xs_status xs_lookup_requests(xs_tables_t h, const xs_request* reqs,
     if (!h->req_event) XS_HIP(hipEventCreateWithFlags(&h->req_event,
                                                       hipEventDisableTiming));
     auto* rd = (ReqDev*)h->req_stage;
+    int64_t tiles = 0, begin = 0;
     for (int i = 0; i < count; ++i) {
       const xs_request& r = reqs[i];
-      if (r.n < 0 || r.n > 0x7fffffffLL)
-        return fail(XS_EINVAL, "request %d: n out of range", i);
-      if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
-        return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
-      rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles};
+      rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles, begin};
       tiles += (r.n + kStreamTile - 1) / kStreamTile;
+      begin += r.n;
     }
-    if (tiles > 0x7fffffffLL) return fail(XS_EINVAL, "batch too large");
     XS_HIP(hipMemcpyAsync(reqs_dev, rd, bytes, hipMemcpyHostToDevice, s));
     XS_HIP(hipEventRecord(h->req_event, s));
   }
   hipLaunchKernelGGL(k_requests_init, dim3((count + 1 + 255) / 256), dim3(256),
                      0, s, stamps, count);
   XS_HIP(hipGetLastError());
-  if (tiles == 0) return XS_OK;
+  if (plan.tiles == 0) return XS_OK;
+  const xs_params& p = plan.p;
+  const dim3 grid((unsigned)plan.tiles), block(kStreamThreads);
+
+  if (plan.batch_sorted) {
+    // Gather every request into one queue, sort and look it up as one
+    // batch, and scatter the results back per request.
+    auto* E_all = (double*)(ws + plan.off_E);
+    auto* m_all = (int32_t*)(ws + plan.off_mat);
+    void* out_all = ws + plan.off_out;
+    hipLaunchKernelGGL(k_requests_gather, grid, block, 0, s, reqs_dev, count,
+                       E_all, m_all, stamps);
+    XS_HIP(hipGetLastError());
+    if (xs_status st = xs_lookup_batch(h, plan.total, E_all, m_all, out_all,
+                                       &p, ws + plan.off_lookup_ws,
+                                       plan.lookup_ws_bytes, stream))
+      return st;
+    if (p.precision == XS_FP64)
+      hipLaunchKernelGGL(k_requests_scatter<double>, grid, block, 0, s,
+                         reqs_dev, count, (const double*)out_all, stamps);
+    else
+      hipLaunchKernelGGL(k_requests_scatter<float>, grid, block, 0, s,
+                         reqs_dev, count, (const float*)out_all, stamps);
+    XS_HIP(hipGetLastError());
+    return XS_OK;
+  }
+
   int64_t bmin;
   int shift;
   energy_key_shift(h, &bmin, &shift);
   hipError_t e;
   switch (p.grid) {
     case XS_GRID_NUCLIDE:
-      e = launch_requests_p<XS_GRID_NUCLIDE>(p, h->d, reqs_dev, count, stamps, tiles, bmin, shift, s);
+      e = launch_requests_p<XS_GRID_NUCLIDE>(p, h->d, reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
       break;
     case XS_GRID_HASH:
-      e = launch_requests_p<XS_GRID_HASH>(p, h->d, reqs_dev, count, stamps, tiles, bmin, shift, s);
+      e = launch_requests_p<XS_GRID_HASH>(p, h->d, reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
       break;
     default:
-      e = launch_requests_p<XS_GRID_UNIONIZED>(p, h->d, reqs_dev, count, stamps, tiles, bmin, shift, s);
+      e = launch_requests_p<XS_GRID_UNIONIZED>(p, h->d, reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
       break;
   }
   if (e != hipSuccess)

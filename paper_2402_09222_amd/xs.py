@@ -228,7 +228,8 @@ def load_library(path: str = LIB_PATH):
         "xs_stream_destroy": ([vp], i32),
         "xs_lookup_requests": ([vp, P(xs_request), i32, P(xs_params), vp, sz, vp],
                                i32),
-        "xs_requests_workspace_size": ([i32, P(sz)], i32),
+        "xs_requests_workspace_size": ([vp, P(xs_request), i32, P(xs_params),
+                                        P(sz)], i32),
         "xs_requests_stats": ([vp, i32, vp, P(xs_request_stats),
                                P(ctypes.c_double)], i32),
         "xs_status_string": ([i32], ctypes.c_char_p),
@@ -619,24 +620,13 @@ def xs_stream_destroy(stream: Stream):
 class RequestBatch:
     """Workspace and descriptors of one xs_lookup_requests call."""
 
-    def __init__(self, count: int, device):
-        b = ctypes.c_size_t()
-        _check(load_library().xs_requests_workspace_size(count, ctypes.byref(b)),
-               "xs_requests_workspace_size")
-        self.keep, self.ptr, self.nbytes = _workspace(b.value, device)
-        self.count = count
+    def __init__(self, nbytes: int, device):
+        self.keep, self.ptr, self.nbytes = _workspace(nbytes, device)
         self.requests = None
+        self.n_req = 0
 
 
-def xs_lookup_requests(tables: Tables, requests, params: xs_params = None,
-                       batch: RequestBatch = None, stream=None) -> RequestBatch:
-    """requests: list of (E, mat, out) device tensors.  Returns the batch
-    object (pass it to xs_requests_stats)."""
-    if not requests:
-        raise ValueError("no requests")
-    dev = requests[0][0].device
-    if batch is None or batch.count < len(requests):
-        batch = RequestBatch(len(requests), dev)
+def _request_array(requests):
     arr = (xs_request * len(requests))()
     for i, (E, mat, out) in enumerate(requests):
         _check_queries(E, mat)
@@ -644,12 +634,43 @@ def xs_lookup_requests(tables: Tables, requests, params: xs_params = None,
             raise ValueError("out must be a contiguous [n, 5] tensor")
         arr[i] = xs_request(E.numel(), E.data_ptr(), mat.data_ptr(),
                             out.data_ptr())
+    return arr
+
+
+def xs_requests_workspace_size(tables: Tables, requests,
+                               params: xs_params = None) -> int:
+    arr = _request_array(requests)
+    b = ctypes.c_size_t()
+    _check(load_library().xs_requests_workspace_size(
+        tables.handle, arr, len(requests),
+        ctypes.byref(params) if params is not None else None, ctypes.byref(b)),
+        "xs_requests_workspace_size")
+    return b.value
+
+
+def xs_lookup_requests(tables: Tables, requests, params: xs_params = None,
+                       batch: RequestBatch = None, stream=None) -> RequestBatch:
+    """requests: list of (E, mat, out) device tensors.  Returns the batch
+    object holding the workspace (pass it to xs_requests_stats, or back in
+    to reuse its workspace)."""
+    if not requests:
+        raise ValueError("no requests")
+    dev = requests[0][0].device
+    arr = _request_array(requests)
+    lib = load_library()
+    pp = ctypes.byref(params) if params is not None else None
+    need = ctypes.c_size_t()
+    _check(lib.xs_requests_workspace_size(tables.handle, arr, len(requests), pp,
+                                          ctypes.byref(need)),
+           "xs_requests_workspace_size")
+    if batch is None or batch.nbytes < need.value:
+        batch = RequestBatch(need.value, dev)
     batch.requests = list(requests)
     batch.n_req = len(requests)
-    _check(load_library().xs_lookup_requests(
-        tables.handle, arr, len(requests),
-        ctypes.byref(params) if params is not None else None, batch.ptr,
-        batch.nbytes, _stream_ptr(stream, dev)), "xs_lookup_requests")
+    _check(lib.xs_lookup_requests(tables.handle, arr, len(requests), pp,
+                                  batch.ptr, batch.nbytes,
+                                  _stream_ptr(stream, dev)),
+           "xs_lookup_requests")
     return batch
 
 

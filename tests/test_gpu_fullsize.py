@@ -156,3 +156,34 @@ def test_indices_match_bisection(full, grid):
     _, idx_ref, off_s = oracle.lookup(t, q.E[:2000], q.mat[:2000],
                                       with_index=True)
     assert np.array_equal(a[:off_s[-1]].cpu().numpy(), idx_ref)
+
+
+@pytest.mark.parametrize("grid,prec", [("unionized", xs.XS_FP64),
+                                       ("hash", xs.XS_FP32)])
+def test_requests_full(full, grid, prec):
+    """Uneven requests over the full-size tables in one launch: FP64 equals
+    the plain batch bit for bit, the FP32 form equals the oracle's samples."""
+    if "out64" not in full:
+        pytest.skip("plain run failed")
+    s = synth.Stream(43, 1)
+    sizes = np.floor(np.exp(np.log(1e3) + s.uniform(60) *
+                            (np.log(3e5) - np.log(1e3)))).astype(np.int64)
+    sizes[7] = 0
+    say("requests full size", grid, prec, int(sizes.sum()), "lookups")
+    dt = torch.float64 if prec == xs.XS_FP64 else torch.float32
+    starts = np.concatenate(([0], np.cumsum(sizes)))
+    reqs = [(full["E"][a:b], full["m"][a:b],
+             torch.empty((b - a, 5), dtype=dt, device="cuda:0"))
+            for a, b in zip(starts[:-1], starts[1:])]
+    p = xs.make_params(prec, grid=grid, unroll=2)
+    batch = xs.xs_lookup_requests(full["h"], reqs, params=p)
+    stats, makespan = xs.xs_requests_stats(batch)
+    assert makespan > 0 and [st["n"] for st in stats] == list(sizes)
+    got = torch.cat([o for _, _, o in reqs]).cpu().numpy()
+    end = int(starts[-1])
+    if prec == xs.XS_FP64:
+        assert np.array_equal(got, full["out64"][:end].numpy())
+    else:
+        sel = full["pick"] < end
+        assert sel.sum() > 100
+        assert np.array_equal(got[full["pick"][sel]], full["ref32"][sel])

@@ -312,3 +312,64 @@ def test_profile_counts(cfg1):
     assert prof["lookups"] == 3 * len(cfg1["q"])
     assert prof["ms_lookup"] > 0 and prof["ms_sort"] > 0
     assert prof["ms_total"] >= prof["ms_lookup"]
+
+
+@pytest.mark.parametrize("union_by_material", [False, True])
+def test_lds_staging_groups(union_by_material):
+    """LDS staging on materials longer than one staging group (70 and 33
+    nuclides) with windows that fit (small blocks) and windows that do not
+    (large blocks, per-lane search for that nuclide): identical bits to the
+    oracle for every grid method and both precisions."""
+    say("lds groups", union_by_material)
+    t = synth.random_tables(17, 80, 500, 3, sizes=[70, 33, 5])
+    q = synth.random_queries(17, t, 60_000)
+    flags = ALL_FLAGS | (xs.XS_BUILD_UNION_BY_MATERIAL if union_by_material
+                         else 0)
+    h = xs.xs_create_tables(t, flags, 1000)
+    try:
+        ref = oracle.lookup(t, q.E, q.mat)
+        ref32 = oracle.lookup_f32(t, q.E, q.mat)
+        E, m = dev(q.E, torch.float64), dev(q.mat, torch.int32)
+        grids = ("unionized",) if union_by_material else (
+            "nuclide", "hash", "unionized")
+        for grid in grids:
+            for bs, sort in ((64, "band_material"), (256, "material_energy"),
+                             (1024, "band_material"), (128, "none")):
+                for prec, r in ((xs.XS_FP64, ref), (xs.XS_FP32, ref32)):
+                    out = run(h, E, m, precision=prec, grid=grid, sort=sort,
+                              sort_threshold=0, block_size=bs,
+                              lookups_per_thread=1, unroll=1, lds_stage=1)
+                    assert np.array_equal(out, r), (grid, bs, sort, prec)
+    finally:
+        h.close()
+
+
+def test_concurrent_streams_share_tables(cfg1):
+    """Several streams using one table handle at once, each with its own
+    workspace (sorted batches), give the oracle's bits."""
+    say("concurrent streams")
+    h, E, m = cfg1["h"], cfg1["E"], cfg1["m"]
+    n = E.numel()
+    k = 4
+    parts = [(i * n // k, (i + 1) * n // k) for i in range(k)]
+    streams = [torch.cuda.Stream() for _ in range(k)]
+    for prec, ref in ((xs.XS_FP64, cfg1["ref"]), (xs.XS_FP32, cfg1["ref32"])):
+        p = xs.make_params(prec, grid="hash", sort="band_material",
+                           sort_threshold=0, block_size=256,
+                           lookups_per_thread=1, unroll=2)
+        dt = torch.float64 if prec == xs.XS_FP64 else torch.float32
+        out = torch.full((n, 5), -1.0, dtype=dt, device="cuda:0")
+        wss = [xs._workspace(xs.xs_workspace_size(h, b - a, p), E.device)
+               for a, b in parts]
+        cur = torch.cuda.current_stream()
+        for rep in range(3):
+            for s in streams:
+                s.wait_stream(cur)
+            for s, (a, b), w in zip(streams, parts, wss):
+                with torch.cuda.stream(s):
+                    xs.xs_lookup_batch(h, E[a:b], m[a:b], out=out[a:b],
+                                       params=p, workspace=w, stream=s)
+            for s in streams:
+                cur.wait_stream(s)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), ref), (prec, rep)
