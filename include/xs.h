@@ -327,10 +327,12 @@ xs_status xs_set_tuned(xs_tables_t tables, int64_t n, const xs_params* p);
 /* Many uneven batches served by one persistent kernel launched from a HIP
  * graph (paper section 5.1: the particle buffer is refilled after each
  * kernel call, and with short kernels launches and queue-count transfers to
- * the host leave bubbles).  Each block of the kernel claims 1024-lookup tiles
- * of the batch with an atomic counter, sorts the tile in LDS by material and
- * energy, looks it up, and stamps the request's first and last tile with the
- * device wall clock.  Results equal xs_lookup_batch's bit for bit. */
+ * the host leave bubbles).  The graph [reset times] -> [persistent kernel]
+ * is built once; before each launch its kernel arguments (request and tile
+ * counts) are rewritten.  The kernel's fixed grid strides over the batch's
+ * 1024-lookup tiles; each block sorts a tile in LDS by material and energy,
+ * looks it up, and stamps the request's first and last tile with the device
+ * wall clock.  Results equal xs_lookup_batch's bit for bit. */
 typedef struct xs_stream_s* xs_stream_t;
 
 typedef struct {
@@ -350,7 +352,8 @@ typedef struct {
 /* Creates a stream for batches of up to max_requests requests on `stream`
  * (a hipStream_t as void*).  params (NULL: all automatic, FP64) fixes the
  * precision, grid method and nuclides in flight; sort, block size, lookups
- * per lane and threshold do not apply.  Captures the graph once. */
+ * per lane and threshold do not apply.  Builds and instantiates the graph
+ * once (allocates; the other stream calls do not). */
 xs_status xs_stream_create(xs_tables_t tables, const xs_params* params,
                            int32_t max_requests, void* stream,
                            xs_stream_t* out);

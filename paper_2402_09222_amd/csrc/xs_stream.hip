@@ -36,17 +36,6 @@ struct ReqDev {
   int64_t begin;       // first position in the batch's concatenated order
 };
 
-struct StreamHeader {
-  int32_t count;       // requests in the batch
-  int32_t pad;
-  int64_t tiles;       // tiles in the batch
-};
-
-struct StreamState {
-  unsigned long long counter;  // next tile to claim
-  unsigned long long t_min;    // earliest tile start of the batch
-};
-
 // Tile sort key: material in the high 16 bits, then the top 16 bits of the
 // energy key; lanes without a lookup sort last.
 __device__ __forceinline__ uint32_t tile_key(double e, int m, int M,
@@ -56,20 +45,6 @@ __device__ __forceinline__ uint32_t tile_key(double e, int m, int M,
   const uint32_t ek = (uint32_t)(d > 0xffff ? 0xffff : d);
   const uint32_t mm = (uint32_t)(m < 0 ? 0 : (m >= M ? M - 1 : m));
   return (mm << 16) | ek;
-}
-
-// Init node of the graph: resets the claim counter and the stamps.
-__global__ void k_stream_init(StreamState* st, unsigned long long* t_first,
-                              unsigned long long* t_last, int max_requests) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    st->counter = 0;
-    st->t_min = ~0ull;
-  }
-  if (i < max_requests) {
-    t_first[i] = ~0ull;
-    t_last[i] = 0;
-  }
 }
 
 // Sorts the tile's lookups in LDS by (material, energy) and looks them up:
@@ -153,36 +128,29 @@ __device__ __forceinline__ int request_of(const ReqDev* reqs, int count,
   return lo;
 }
 
+// Persistent form for request streams: a fixed grid (a few blocks per
+// compute unit) strides over the batch's tiles.  The tile count and the
+// request count are kernel arguments, rewritten in the instantiated graph
+// before every launch, so the loop bound never comes from device memory and
+// every block leaves after at most ceil(tiles / gridDim) tiles.
 template <int GRID, int PREC, int U>
 __global__ __launch_bounds__(kStreamThreads) void k_stream(
-    const DevTables t, const StreamHeader* __restrict__ hdr,
-    const ReqDev* __restrict__ reqs, StreamState* st,
-    unsigned long long* t_first, unsigned long long* t_last,
-    int64_t ebits_min, int eshift) {
+    const DevTables t, const ReqDev* __restrict__ reqs, int count,
+    int64_t tiles, unsigned long long* stamps, int64_t ebits_min, int eshift) {
   __shared__ uint32_t skey[kStreamTile];
   __shared__ uint16_t sidx[kStreamTile];
-  __shared__ unsigned long long claim;
-  const int tid = threadIdx.x;
-  const int count = hdr->count;
-  const int64_t tiles = hdr->tiles;
-
-  for (;;) {
-    if (tid == 0) claim = atomicAdd(&st->counter, 1ull);
-    __syncthreads();
-    const int64_t g = (int64_t)claim;
-    __syncthreads();
-    if (g >= tiles) break;  // every block reaches this once the batch is done
+  for (int64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
     const unsigned long long t0 = wall_clock64();
     const int r = request_of(reqs, count, g);
     const ReqDev R = reqs[r];
     process_tile<GRID, PREC, U>(t, R, (g - R.tile_begin) * kStreamTile, skey,
                                 sidx, ebits_min, eshift);
-    __syncthreads();  // the tile's LDS is reused by the next claim
-    if (tid == 0) {
+    __syncthreads();  // the tile's LDS is reused by the next tile
+    if (threadIdx.x == 0) {
       const unsigned long long t1 = wall_clock64();
-      atomicMin(&t_first[r], t0);
-      atomicMax(&t_last[r], t1);
-      atomicMin(&st->t_min, t0);
+      atomicMin(&stamps[2 * r], t0);
+      atomicMax(&stamps[2 * r + 1], t1);
+      atomicMin(&stamps[2 * count], t0);
     }
   }
 }
@@ -270,253 +238,6 @@ __global__ __launch_bounds__(kStreamThreads) void k_requests_scatter(
 }  // namespace
 }  // namespace xs
 
-struct xs_stream_s {
-  xs_tables_t tables = nullptr;
-  xs_params params{};
-  hipStream_t user = nullptr;
-  hipStream_t capture = nullptr;
-  int32_t max_requests = 0;
-  int32_t pending = 0;  // requests of the batch in flight (0 = idle)
-  xs::StreamHeader* hdr_dev = nullptr;
-  xs::ReqDev* reqs_dev = nullptr;
-  xs::StreamState* state_dev = nullptr;
-  unsigned long long* t_first_dev = nullptr;
-  unsigned long long* t_last_dev = nullptr;
-  void* host = nullptr;  // pinned: header + descriptors
-  int64_t n_req[1] = {0};
-  std::vector<int64_t> sizes;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipEvent_t done = nullptr;
-  int blocks = 0;
-  double clock_khz = 0;
-};
-
-namespace xs {
-namespace {
-
-void stream_release(xs_stream_s* s) {
-  if (s->exec) (void)hipGraphExecDestroy(s->exec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
-  if (s->done) (void)hipEventDestroy(s->done);
-  if (s->capture) (void)hipStreamDestroy(s->capture);
-  for (void* p : {(void*)s->hdr_dev, (void*)s->reqs_dev, (void*)s->state_dev,
-                  (void*)s->t_first_dev, (void*)s->t_last_dev})
-    if (p) (void)hipFree(p);
-  if (s->host) (void)hipHostFree(s->host);
-  delete s;
-}
-
-template <int GRID, int PREC, int U>
-hipError_t launch_stream_kernel(xs_stream_s* s, hipStream_t st) {
-  const DevTables& t = s->tables->d;
-  const int64_t ebits_min = [&] {
-    int64_t b;
-    std::memcpy(&b, &s->tables->info.e_min, 8);
-    return b;
-  }();
-  int64_t span;
-  {
-    int64_t bmax;
-    std::memcpy(&bmax, &s->tables->info.e_max, 8);
-    span = bmax - ebits_min;
-  }
-  int shift = 0;
-  while ((span >> shift) > 0xffff) ++shift;
-  hipLaunchKernelGGL((k_stream<GRID, PREC, U>), dim3(s->blocks),
-                     dim3(kStreamThreads), 0, st, t, s->hdr_dev, s->reqs_dev,
-                     s->state_dev, s->t_first_dev, s->t_last_dev, ebits_min,
-                     shift);
-  return hipGetLastError();
-}
-
-template <int GRID, int PREC>
-hipError_t launch_stream_u(xs_stream_s* s, hipStream_t st) {
-  switch (s->params.unroll) {
-    case 1: return launch_stream_kernel<GRID, PREC, 1>(s, st);
-    case 2: return launch_stream_kernel<GRID, PREC, 2>(s, st);
-    default: return launch_stream_kernel<GRID, PREC, 4>(s, st);
-  }
-}
-
-template <int GRID>
-hipError_t launch_stream_p(xs_stream_s* s, hipStream_t st) {
-  return s->params.precision == XS_FP64 ? launch_stream_u<GRID, XS_FP64>(s, st)
-                                        : launch_stream_u<GRID, XS_FP32>(s, st);
-}
-
-hipError_t launch_stream(xs_stream_s* s, hipStream_t st) {
-  switch (s->params.grid) {
-    case XS_GRID_NUCLIDE: return launch_stream_p<XS_GRID_NUCLIDE>(s, st);
-    case XS_GRID_HASH: return launch_stream_p<XS_GRID_HASH>(s, st);
-    default: return launch_stream_p<XS_GRID_UNIONIZED>(s, st);
-  }
-}
-
-}  // namespace
-}  // namespace xs
-
-using namespace xs;
-
-extern "C" {
-
-xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
-                           int32_t max_requests, void* stream,
-                           xs_stream_t* out) {
-  clear_error();
-  if (!h || !out) return fail(XS_EINVAL, "tables and out must not be NULL");
-  if (max_requests < 1 || max_requests > (1 << 20))
-    return fail(XS_EINVAL, "max_requests must be in [1, 2^20]");
-  xs_params p;
-  // Resolved like a large batch; sort, block size, lookups per lane and the
-  // threshold do not apply (tiles are sorted in LDS, blocks are 256 lanes).
-  if (xs_status st = xs_resolve_params(h, 1 << 20, params, &p)) return st;
-  auto* s = new (std::nothrow) xs_stream_s();
-  if (!s) return fail(XS_ENOMEM, "host allocation failed");
-  s->tables = h;
-  s->params = p;
-  s->user = (hipStream_t)stream;
-  s->max_requests = max_requests;
-  auto bail = [&](xs_status st) {
-    stream_release(s);
-    return st;
-  };
-  auto hip = [&](hipError_t e, const char* what) -> xs_status {
-    if (e == hipSuccess) return XS_OK;
-    return fail(e == hipErrorOutOfMemory ? XS_ENOMEM : XS_EHIP, "%s: %s", what,
-                hipGetErrorString(e));
-  };
-  xs_status st;
-  const size_t req_bytes = sizeof(ReqDev) * (size_t)max_requests;
-  if ((st = hip(hipMalloc(&s->hdr_dev, sizeof(StreamHeader)), "hipMalloc")) ||
-      (st = hip(hipMalloc(&s->reqs_dev, req_bytes), "hipMalloc")) ||
-      (st = hip(hipMalloc(&s->state_dev, sizeof(StreamState)), "hipMalloc")) ||
-      (st = hip(hipMalloc(&s->t_first_dev, 8 * (size_t)max_requests), "hipMalloc")) ||
-      (st = hip(hipMalloc(&s->t_last_dev, 8 * (size_t)max_requests), "hipMalloc")) ||
-      (st = hip(hipHostMalloc(&s->host, sizeof(StreamHeader) + req_bytes),
-                "hipHostMalloc")) ||
-      (st = hip(hipEventCreateWithFlags(&s->done, hipEventDisableTiming),
-                "hipEventCreate")) ||
-      (st = hip(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking),
-                "hipStreamCreate")))
-    return bail(st);
-  int dev = 0, cus = 0, khz = 0;
-  if ((st = hip(hipGetDevice(&dev), "hipGetDevice")) ||
-      (st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                      dev), "hipDeviceGetAttribute")) ||
-      (st = hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev),
-                "hipDeviceGetAttribute")))
-    return bail(st);
-  s->blocks = std::max(1, cus) * 8;
-  s->clock_khz = khz > 0 ? khz : 100000.0;
-
-  // Capture [init, persistent kernel] once; every submit replays it.
-  if ((st = hip(hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal),
-                "hipStreamBeginCapture")))
-    return bail(st);
-  hipLaunchKernelGGL(k_stream_init, dim3((max_requests + 255) / 256), dim3(256),
-                     0, s->capture, s->state_dev, s->t_first_dev,
-                     s->t_last_dev, max_requests);
-  hipError_t le = hipGetLastError();
-  if (le == hipSuccess) le = launch_stream(s, s->capture);
-  hipError_t ce = hipStreamEndCapture(s->capture, &s->graph);
-  if ((st = hip(le, "stream kernel launch")) || (st = hip(ce, "hipStreamEndCapture")))
-    return bail(st);
-  if ((st = hip(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0),
-                "hipGraphInstantiate")))
-    return bail(st);
-  *out = s;
-  return XS_OK;
-}
-
-xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
-                           int32_t count) {
-  clear_error();
-  if (!s) return fail(XS_EINVAL, "stream is NULL");
-  if (s->pending) return fail(XS_EINVAL, "a batch is still in flight; call "
-                              "xs_stream_wait first");
-  if (count < 1 || count > s->max_requests)
-    return fail(XS_EINVAL, "count must be in [1, %d]", s->max_requests);
-  if (!reqs) return fail(XS_EINVAL, "reqs is NULL");
-  auto* hdr = (StreamHeader*)s->host;
-  auto* rd = (ReqDev*)(hdr + 1);
-  int64_t tiles = 0;
-  s->sizes.assign(count, 0);
-  for (int i = 0; i < count; ++i) {
-    const xs_request& r = reqs[i];
-    if (r.n < 0 || r.n > 0x7fffffffLL)
-      return fail(XS_EINVAL, "request %d: n out of range", i);
-    if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
-      return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
-    rd[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles, 0};
-    tiles += (r.n + kStreamTile - 1) / kStreamTile;
-    s->sizes[i] = r.n;
-  }
-  hdr->count = count;
-  hdr->pad = 0;
-  hdr->tiles = tiles;
-  XS_HIP(hipMemcpyAsync(s->hdr_dev, hdr, sizeof(StreamHeader),
-                        hipMemcpyHostToDevice, s->user));
-  XS_HIP(hipMemcpyAsync(s->reqs_dev, rd, sizeof(ReqDev) * count,
-                        hipMemcpyHostToDevice, s->user));
-  XS_HIP(hipGraphLaunch(s->exec, s->user));
-  XS_HIP(hipEventRecord(s->done, s->user));
-  s->pending = count;
-  return XS_OK;
-}
-
-xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
-                         double* makespan_us) {
-  clear_error();
-  if (!s) return fail(XS_EINVAL, "stream is NULL");
-  if (!s->pending) return fail(XS_EINVAL, "no batch in flight");
-  XS_HIP(hipEventSynchronize(s->done));
-  const int count = s->pending;
-  s->pending = 0;
-  std::vector<unsigned long long> a(count), b(count);
-  StreamState state;
-  XS_HIP(hipMemcpy(a.data(), s->t_first_dev, 8 * (size_t)count,
-                   hipMemcpyDeviceToHost));
-  XS_HIP(hipMemcpy(b.data(), s->t_last_dev, 8 * (size_t)count,
-                   hipMemcpyDeviceToHost));
-  XS_HIP(hipMemcpy(&state, s->state_dev, sizeof(state), hipMemcpyDeviceToHost));
-  const double us_per_tick = 1000.0 / s->clock_khz;
-  unsigned long long tmax = 0;
-  for (int i = 0; i < count; ++i) tmax = std::max(tmax, b[i]);
-  if (makespan_us)
-    *makespan_us = state.t_min == ~0ull ? 0.0 : (tmax - state.t_min) * us_per_tick;
-  if (stats) {
-    for (int i = 0; i < count; ++i) {
-      xs_request_stats& r = stats[i];
-      r.n = s->sizes[i];
-      if (a[i] == ~0ull) {
-        r.start_us = r.end_us = r.latency_us = 0.0;
-        continue;
-      }
-      r.start_us = (a[i] - state.t_min) * us_per_tick;
-      r.end_us = (b[i] - state.t_min) * us_per_tick;
-      r.latency_us = r.end_us - r.start_us;
-    }
-  }
-  return XS_OK;
-}
-
-xs_status xs_stream_params(xs_stream_t s, xs_params* out) {
-  clear_error();
-  if (!s || !out) return fail(XS_EINVAL, "stream and out must not be NULL");
-  *out = s->params;
-  return XS_OK;
-}
-
-xs_status xs_stream_destroy(xs_stream_t s) {
-  clear_error();
-  if (!s) return XS_OK;
-  if (s->pending) (void)hipEventSynchronize(s->done);
-  stream_release(s);
-  return XS_OK;
-}
-
-}  // extern "C"
 
 // ---- one launch for a batch of requests ------------------------------------
 
@@ -624,6 +345,8 @@ xs_status plan_requests(xs_tables_t h, const xs_request* reqs, int32_t count,
 
 }  // namespace
 }  // namespace xs
+
+using namespace xs;
 
 extern "C" {
 
@@ -765,6 +488,274 @@ xs_status xs_requests_stats(const void* d_ws, int32_t count, void* stream,
       r.latency_us = r.end_us - r.start_us;
     }
   }
+  return XS_OK;
+}
+
+}  // extern "C"
+
+// ---- request streams: the persistent kernel in a reusable graph ------------
+
+struct xs_stream_s {
+  xs_tables_t tables = nullptr;
+  xs_params params{};
+  hipStream_t user = nullptr;
+  int32_t max_requests = 0;
+  int32_t pending = 0;  // requests of the batch in flight (0 = idle)
+  xs::ReqDev* reqs_dev = nullptr;
+  unsigned long long* stamps_dev = nullptr;  // 2 * max_requests + 1
+  xs::ReqDev* host = nullptr;                // pinned staging of descriptors
+  std::vector<int64_t> sizes;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t init_node = nullptr, run_node = nullptr;
+  hipEvent_t done = nullptr;
+  int blocks = 0;
+  double clock_khz = 0;
+  // kernel arguments of the two graph nodes (rewritten before each launch)
+  xs::DevTables a_t{};
+  const xs::ReqDev* a_reqs = nullptr;
+  unsigned long long* a_stamps = nullptr;
+  int a_count = 0;
+  int64_t a_tiles = 0;
+  int64_t a_bmin = 0;
+  int a_shift = 0;
+  void* run_args[7] = {};
+  void* init_args[2] = {};
+  const void* run_func = nullptr;
+};
+
+namespace xs {
+namespace {
+
+void stream_release(xs_stream_s* s) {
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->done) (void)hipEventDestroy(s->done);
+  if (s->reqs_dev) (void)hipFree(s->reqs_dev);
+  if (s->stamps_dev) (void)hipFree(s->stamps_dev);
+  if (s->host) (void)hipHostFree(s->host);
+  delete s;
+}
+
+template <int GRID, int PREC>
+const void* stream_func_p(int unroll) {
+  switch (unroll) {
+    case 1: return (const void*)&k_stream<GRID, PREC, 1>;
+    case 2: return (const void*)&k_stream<GRID, PREC, 2>;
+    default: return (const void*)&k_stream<GRID, PREC, 4>;
+  }
+}
+
+const void* stream_func(const xs_params& p) {
+  switch (p.grid) {
+    case XS_GRID_NUCLIDE:
+      return p.precision == XS_FP64 ? stream_func_p<XS_GRID_NUCLIDE, XS_FP64>(p.unroll)
+                                    : stream_func_p<XS_GRID_NUCLIDE, XS_FP32>(p.unroll);
+    case XS_GRID_HASH:
+      return p.precision == XS_FP64 ? stream_func_p<XS_GRID_HASH, XS_FP64>(p.unroll)
+                                    : stream_func_p<XS_GRID_HASH, XS_FP32>(p.unroll);
+    default:
+      return p.precision == XS_FP64 ? stream_func_p<XS_GRID_UNIONIZED, XS_FP64>(p.unroll)
+                                    : stream_func_p<XS_GRID_UNIONIZED, XS_FP32>(p.unroll);
+  }
+}
+
+hipKernelNodeParams init_params(xs_stream_s* s) {
+  hipKernelNodeParams kp{};
+  kp.func = (void*)&k_requests_init;
+  kp.gridDim = dim3((s->max_requests + 1 + 255) / 256);
+  kp.blockDim = dim3(256);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = s->init_args;
+  kp.extra = nullptr;
+  return kp;
+}
+
+hipKernelNodeParams run_params(xs_stream_s* s) {
+  hipKernelNodeParams kp{};
+  kp.func = (void*)s->run_func;
+  kp.gridDim = dim3(s->blocks);
+  kp.blockDim = dim3(kStreamThreads);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = s->run_args;
+  kp.extra = nullptr;
+  return kp;
+}
+
+}  // namespace
+}  // namespace xs
+
+extern "C" {
+
+xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
+                           int32_t max_requests, void* stream,
+                           xs_stream_t* out) {
+  clear_error();
+  if (!h || !out) return fail(XS_EINVAL, "tables and out must not be NULL");
+  if (max_requests < 1 || max_requests > (1 << 20))
+    return fail(XS_EINVAL, "max_requests must be in [1, 2^20]");
+  xs_params p;
+  // Resolved like a large batch; sort, block size, lookups per lane and the
+  // threshold do not apply (tiles are sorted in LDS, blocks are 256 lanes).
+  if (xs_status st = xs_resolve_params(h, 1 << 20, params, &p)) return st;
+  auto* s = new (std::nothrow) xs_stream_s();
+  if (!s) return fail(XS_ENOMEM, "host allocation failed");
+  s->tables = h;
+  s->params = p;
+  s->user = (hipStream_t)stream;
+  s->max_requests = max_requests;
+  auto bail = [&](xs_status st) {
+    stream_release(s);
+    return st;
+  };
+  auto hip = [&](hipError_t e, const char* what) -> xs_status {
+    if (e == hipSuccess) return XS_OK;
+    return fail(e == hipErrorOutOfMemory ? XS_ENOMEM : XS_EHIP, "%s: %s", what,
+                hipGetErrorString(e));
+  };
+  xs_status st;
+  const size_t req_bytes = sizeof(ReqDev) * (size_t)max_requests;
+  if ((st = hip(hipMalloc(&s->reqs_dev, req_bytes), "hipMalloc")) ||
+      (st = hip(hipMalloc(&s->stamps_dev, 8 * (2 * (size_t)max_requests + 1)),
+                "hipMalloc")) ||
+      (st = hip(hipHostMalloc(&s->host, req_bytes), "hipHostMalloc")) ||
+      (st = hip(hipEventCreateWithFlags(&s->done, hipEventDisableTiming),
+                "hipEventCreate")))
+    return bail(st);
+  int dev = 0, cus = 0, khz = 0;
+  if ((st = hip(hipGetDevice(&dev), "hipGetDevice")) ||
+      (st = hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                      dev), "hipDeviceGetAttribute")) ||
+      (st = hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev),
+                "hipDeviceGetAttribute")))
+    return bail(st);
+  if (dev != h->device)
+    return bail(fail(XS_EINVAL, "current device %d is not the tables' device %d",
+                     dev, h->device));
+  s->blocks = std::max(1, cus) * 4;
+  s->clock_khz = khz > 0 ? khz : 100000.0;
+
+  // Kernel arguments live in the handle; the nodes point at them.
+  s->a_t = h->d;
+  s->a_reqs = s->reqs_dev;
+  s->a_stamps = s->stamps_dev;
+  s->a_count = 0;
+  s->a_tiles = 0;
+  energy_key_shift(h, &s->a_bmin, &s->a_shift);
+  s->run_args[0] = &s->a_t;
+  s->run_args[1] = &s->a_reqs;
+  s->run_args[2] = &s->a_count;
+  s->run_args[3] = &s->a_tiles;
+  s->run_args[4] = &s->a_stamps;
+  s->run_args[5] = &s->a_bmin;
+  s->run_args[6] = &s->a_shift;
+  s->init_args[0] = &s->a_stamps;
+  s->init_args[1] = &s->a_count;
+  s->run_func = stream_func(p);
+
+  // The graph [reset stamps] -> [persistent kernel], built node by node.
+  const hipKernelNodeParams ip = init_params(s), rp = run_params(s);
+  if ((st = hip(hipGraphCreate(&s->graph, 0), "hipGraphCreate")) ||
+      (st = hip(hipGraphAddKernelNode(&s->init_node, s->graph, nullptr, 0, &ip),
+                "hipGraphAddKernelNode")) ||
+      (st = hip(hipGraphAddKernelNode(&s->run_node, s->graph, &s->init_node, 1,
+                                      &rp), "hipGraphAddKernelNode")) ||
+      (st = hip(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0),
+                "hipGraphInstantiate")))
+    return bail(st);
+  *out = s;
+  return XS_OK;
+}
+
+xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
+                           int32_t count) {
+  clear_error();
+  if (!s) return fail(XS_EINVAL, "stream is NULL");
+  if (s->pending) return fail(XS_EINVAL, "a batch is still in flight; call "
+                              "xs_stream_wait first");
+  if (count < 1 || count > s->max_requests)
+    return fail(XS_EINVAL, "count must be in [1, %d]", s->max_requests);
+  if (!reqs) return fail(XS_EINVAL, "reqs is NULL");
+  int64_t tiles = 0, begin = 0;
+  for (int i = 0; i < count; ++i) {
+    const xs_request& r = reqs[i];
+    if (r.n < 0 || r.n > 0x7fffffffLL)
+      return fail(XS_EINVAL, "request %d: n out of range", i);
+    if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
+      return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
+    tiles += (r.n + kStreamTile - 1) / kStreamTile;
+    begin += r.n;
+  }
+  if (tiles > 0x7fffffffLL) return fail(XS_EINVAL, "batch too large");
+  // The previous batch has been waited for, so the staging buffer is free.
+  s->sizes.assign(count, 0);
+  tiles = 0;
+  begin = 0;
+  for (int i = 0; i < count; ++i) {
+    const xs_request& r = reqs[i];
+    s->host[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles, begin};
+    tiles += (r.n + kStreamTile - 1) / kStreamTile;
+    begin += r.n;
+    s->sizes[i] = r.n;
+  }
+  s->a_count = count;
+  s->a_tiles = tiles;
+  const hipKernelNodeParams ip = init_params(s), rp = run_params(s);
+  XS_HIP(hipGraphExecKernelNodeSetParams(s->exec, s->init_node, &ip));
+  XS_HIP(hipGraphExecKernelNodeSetParams(s->exec, s->run_node, &rp));
+  XS_HIP(hipMemcpyAsync(s->reqs_dev, s->host, sizeof(ReqDev) * count,
+                        hipMemcpyHostToDevice, s->user));
+  XS_HIP(hipGraphLaunch(s->exec, s->user));
+  XS_HIP(hipEventRecord(s->done, s->user));
+  s->pending = count;
+  return XS_OK;
+}
+
+xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
+                         double* makespan_us) {
+  clear_error();
+  if (!s) return fail(XS_EINVAL, "stream is NULL");
+  if (!s->pending) return fail(XS_EINVAL, "no batch in flight");
+  XS_HIP(hipEventSynchronize(s->done));
+  const int count = s->pending;
+  s->pending = 0;
+  std::vector<unsigned long long> st(2 * (size_t)count + 1);
+  XS_HIP(hipMemcpy(st.data(), s->stamps_dev, 8 * st.size(),
+                   hipMemcpyDeviceToHost));
+  const double us_per_tick = 1000.0 / s->clock_khz;
+  const unsigned long long t0 = st[2 * (size_t)count];
+  unsigned long long tmax = t0;
+  for (int i = 0; i < count; ++i)
+    if (st[2 * i] != ~0ull) tmax = std::max(tmax, st[2 * i + 1]);
+  if (makespan_us) *makespan_us = t0 == ~0ull ? 0.0 : (tmax - t0) * us_per_tick;
+  if (stats) {
+    for (int i = 0; i < count; ++i) {
+      xs_request_stats& r = stats[i];
+      r.n = s->sizes[i];
+      if (st[2 * i] == ~0ull) {
+        r.start_us = r.end_us = r.latency_us = 0.0;
+        continue;
+      }
+      r.start_us = (st[2 * i] - t0) * us_per_tick;
+      r.end_us = (st[2 * i + 1] - t0) * us_per_tick;
+      r.latency_us = r.end_us - r.start_us;
+    }
+  }
+  return XS_OK;
+}
+
+xs_status xs_stream_params(xs_stream_t s, xs_params* out) {
+  clear_error();
+  if (!s || !out) return fail(XS_EINVAL, "stream and out must not be NULL");
+  *out = s->params;
+  return XS_OK;
+}
+
+xs_status xs_stream_destroy(xs_stream_t s) {
+  clear_error();
+  if (!s) return XS_OK;
+  if (s->pending) (void)hipEventSynchronize(s->done);
+  stream_release(s);
   return XS_OK;
 }
 

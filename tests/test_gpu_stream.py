@@ -14,10 +14,13 @@ torch = pytest.importorskip("torch")
 pytestmark = [
     pytest.mark.gpu,
     pytest.mark.skip(reason=(
-        "the first run of these tests on the GPU went silent for 180 s inside "
-        "test_stream_matches_oracle[nuclide-1-0] and was killed; no cause has "
-        "been shown in the stream code yet, so the persistent-stream path "
-        "stays off the GPU until one is")),
+        "the first run of these tests on the GPU (a stream-captured graph "
+        "whose blocks claimed tiles with an atomic counter) went silent for "
+        "180 s inside test_stream_matches_oracle[nuclide-1-0] and was "
+        "killed; no cause has been shown, and the rebuilt path (graph built "
+        "node by node, striding persistent grid, counts as kernel arguments) "
+        "removes differences without a shown cause, so the case stays off "
+        "the GPU")),
 ]
 
 from paper_2402_09222_amd import xs  # noqa: E402
