@@ -485,6 +485,61 @@ def stream_study(args, torch, synth, xs):
     return 0
 
 
+def event_study(args, torch, synth, xs):
+    """The toy event loop (xs_event_run) on the full-size tables: 2M
+    histories through buffers of 2.5e5 and 1e6 particles in flight, queued
+    (compaction) against queueless (predicated) lookups, sorted (banded,
+    threshold 20,000) against unsorted, FP32 form with the tuned grid
+    method.  Histories/s is the paper's figure of merit (particles/s)."""
+    t = synth.config2_tables()
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    h = xs.xs_create_tables(t, flags, args.bins)
+    H = args.event_histories
+    rows = []
+    for slots in (250_000, 1_000_000):
+        q = synth.config4_queries(2, slots)
+        E = torch.from_numpy(q.E).to("cuda:0")
+        m = torch.from_numpy(q.mat).to("cuda:0")
+        xs.xs_tune(h, E, m, xs.xs_tune_config_default(
+            precision=xs.XS_FP32, max_evals=args.tune_evals, reps=3))
+        tuned = xs.xs_resolve_params(h, slots, xs.xs_params_default(xs.XS_FP32))
+        for queue in (xs.XS_QUEUE_COMPACT, xs.XS_QUEUE_PREDICATED):
+            for sort in ("none", "band_material"):
+                p = xs.make_params(xs.XS_FP32, grid=tuned.grid, sort=sort,
+                                   sort_threshold=20000, queue=queue,
+                                   block_size=tuned.block_size,
+                                   lookups_per_thread=tuned.lookups_per_thread,
+                                   unroll=tuned.unroll,
+                                   lds_stage=tuned.lds_stage)
+                best = None
+                for rep in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res, _ = xs.xs_event_run(h, slots, H, 1000 + rep, params=p)
+                    torch.cuda.synchronize()
+                    sec = time.perf_counter() - t0
+                    if best is None or sec < best[0]:
+                        best = (sec, res)
+                sec, res = best
+                row = {"slots": slots,
+                       "queue": "queued" if queue == 0 else "queueless",
+                       "sort": sort, "params": p.as_dict(), "s": sec,
+                       "histories_per_s": H / sec,
+                       "lookups_per_s": res["lookups"] / sec,
+                       "iterations": res["iterations"],
+                       "lookups": res["lookups"]}
+                rows.append(row)
+                log(f"slots {slots} {row['queue']} {sort}: "
+                    f"{row['histories_per_s']:.4g} histories/s, "
+                    f"{row['lookups_per_s']:.4g} lookups/s, "
+                    f"{res['iterations']} iterations")
+    print(json.dumps({"study": "event loop", "histories": H, "rows": rows}),
+          flush=True)
+    h.close()
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,6 +568,10 @@ def main(argv=None):
                          "tuning space (evaluations to the optimum)")
     ap.add_argument("--study-n", type=int, default=4_000_000)
     ap.add_argument("--study-seeds", type=int, default=20)
+    ap.add_argument("--event", action="store_true",
+                    help="toy event loop: histories/s, queued vs queueless, "
+                         "sorted vs unsorted")
+    ap.add_argument("--event-histories", type=int, default=2_000_000)
     ap.add_argument("--streams", action="store_true",
                     help="one batch split over 1, 2, 4, 8 concurrent streams")
     ap.add_argument("--energy", action="store_true",
@@ -545,6 +604,8 @@ def main(argv=None):
               flush=True)
         return 0
 
+    if args.event:
+        return event_study(args, torch, synth, xs)
     if args.streams:
         return stream_study(args, torch, synth, xs)
     if args.energy:

@@ -411,6 +411,66 @@ xs_status xs_requests_workspace_size(xs_tables_t tables, const xs_request* reqs,
 xs_status xs_requests_stats(const void* d_ws, int32_t count, void* stream,
                             xs_request_stats* stats, double* makespan_us);
 
+/* ---- a toy event loop around the lookup ---------------------------------- */
+
+/* The shape of the paper's event-based transport (section 5.1): a buffer of
+ * n_slots particles in flight; each iteration looks up the live slots
+ * (xs_lookup_active, so params' queue mode, sort policy and threshold
+ * apply), then one kernel collides every live particle and refills dead
+ * slots from the source until n_histories histories have run.  The
+ * collision uses the first two channels S0, S1 and three uniform numbers
+ * u0..u2 of (seed, history, collision) from SplitMix64 at counter
+ * history * 2^20 + collision * 4 + draw:
+ *   absorbed (fate 1)              if u0 * (S0 + S1) < 0.25 * S1
+ *   else E' = E * (0.2 + 0.8 * u1); cut off (fate 2) if E' < e_cut;
+ *   collision limit (fate 3)       at collision 2^18 - 1;
+ *   else m' = min(floor((u2 * 5) * M), M - 1) when u2 < 0.2.
+ * A source particle of history h has E = 0.01 + 0.99 * v0 and
+ * m = min(floor(v1 * M), M - 1), v = the draws of collision 0.  All of it is
+ * FP64 +, -, * and compares, so each history's outcome is exact and does
+ * not depend on the slot or iteration that ran it. */
+typedef struct {
+  int64_t n_slots;         /* particles in flight, 1 .. 2^31 - 1 */
+  int64_t n_histories;     /* histories to run, 0 .. 2^40 */
+  uint64_t seed;
+  double e_cut;            /* > 0 */
+  int32_t check_every;     /* iterations between completion checks, >= 1 */
+  int32_t max_iterations;  /* bound on iterations, >= 1 */
+} xs_event_config;
+
+typedef struct {           /* DEVICE buffers owned by the caller */
+  double* E;               /* [n_slots] */
+  int32_t* mat;            /* [n_slots] */
+  uint8_t* alive;          /* [n_slots] */
+  int64_t* hist;           /* [n_slots] history of the slot */
+  int32_t* ncoll;          /* [n_slots] collisions so far */
+  void* sigma;             /* [n_slots][5] of the lookup precision */
+  int64_t* counters;       /* [3]: next history, finished, lookups run */
+  int32_t* t_collisions;   /* [n_histories] collisions of each history */
+  double* t_energy;        /* [n_histories] energy at its end */
+  uint8_t* t_fate;         /* [n_histories] 1 absorbed, 2 cut off, 3 limit */
+} xs_event_buffers;
+
+typedef struct {
+  int64_t iterations;      /* event iterations run */
+  int64_t lookups;         /* (particle, iteration) lookups */
+  int64_t histories;       /* histories finished */
+} xs_event_result;
+
+/* Workspace for xs_event_run (that of n_slots lookups with params). */
+xs_status xs_event_workspace_size(xs_tables_t tables, const xs_event_config* cfg,
+                                  const xs_params* params, size_t* bytes);
+
+/* Runs the loop on `stream` until every history has finished, reading the
+ * finished count to the host every check_every iterations (the paper's
+ * queue-count transfer).  XS_ETIMEOUT if max_iterations pass first (the
+ * tallies of finished histories are valid); XS_EINVAL for bad sizes or NULL
+ * buffers. */
+xs_status xs_event_run(xs_tables_t tables, const xs_event_config* cfg,
+                       const xs_event_buffers* bufs, const xs_params* params,
+                       void* d_ws, size_t ws_bytes, void* stream,
+                       xs_event_result* result);
+
 /* ---- measurement --------------------------------------------------------- */
 
 /* Starts recording per-stage HIP events for subsequent lookup calls on this

@@ -168,6 +168,31 @@ class xs_request_stats(ctypes.Structure):
     ]
 
 
+class xs_event_config(ctypes.Structure):
+    _fields_ = [
+        ("n_slots", ctypes.c_int64),
+        ("n_histories", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("e_cut", ctypes.c_double),
+        ("check_every", ctypes.c_int32),
+        ("max_iterations", ctypes.c_int32),
+    ]
+
+
+class xs_event_buffers(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in (
+        "E", "mat", "alive", "hist", "ncoll", "sigma", "counters",
+        "t_collisions", "t_energy", "t_fate")]
+
+
+class xs_event_result(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int64),
+        ("lookups", ctypes.c_int64),
+        ("histories", ctypes.c_int64),
+    ]
+
+
 XS_TUNE_EXHAUSTIVE, XS_TUNE_FOREST = 0, 1
 EVAL_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(xs_params),
                            ctypes.c_double, ctypes.POINTER(ctypes.c_double),
@@ -232,6 +257,10 @@ def load_library(path: str = LIB_PATH):
                                         P(sz)], i32),
         "xs_requests_stats": ([vp, i32, vp, P(xs_request_stats),
                                P(ctypes.c_double)], i32),
+        "xs_event_workspace_size": ([vp, P(xs_event_config), P(xs_params),
+                                     P(sz)], i32),
+        "xs_event_run": ([vp, P(xs_event_config), P(xs_event_buffers),
+                          P(xs_params), vp, sz, vp, P(xs_event_result)], i32),
         "xs_status_string": ([i32], ctypes.c_char_p),
         "xs_last_error": ([], ctypes.c_char_p),
     }
@@ -686,3 +715,56 @@ def xs_requests_stats(batch: RequestBatch, stream=None):
            "xs_requests_stats")
     return [dict(n=s.n, start_us=s.start_us, end_us=s.end_us,
                  latency_us=s.latency_us) for s in stats], mk.value
+
+
+def xs_event_run(tables: Tables, n_slots: int, n_histories: int, seed: int,
+                 params: xs_params = None, e_cut: float = 1e-5,
+                 check_every: int = 8, max_iterations: int = 1 << 20,
+                 device="cuda:0", stream=None, workspace=None):
+    """Runs the toy event loop; returns (result dict, tallies dict of
+    device tensors: collisions int32, energy float64, fate uint8, each
+    [n_histories])."""
+    import torch
+    prec = XS_FP64 if params is None else params.precision
+    if prec == XS_AUTO:
+        prec = XS_FP64
+    dt = torch.float64 if prec == XS_FP64 else torch.float32
+    dev = torch.device(device)
+    buf = {
+        "E": torch.empty(n_slots, dtype=torch.float64, device=dev),
+        "mat": torch.empty(n_slots, dtype=torch.int32, device=dev),
+        "alive": torch.zeros(n_slots, dtype=torch.uint8, device=dev),
+        "hist": torch.empty(n_slots, dtype=torch.int64, device=dev),
+        "ncoll": torch.empty(n_slots, dtype=torch.int32, device=dev),
+        "sigma": torch.empty((n_slots, XS_CHANNELS), dtype=dt, device=dev),
+        "counters": torch.zeros(3, dtype=torch.int64, device=dev),
+        "t_collisions": torch.zeros(max(n_histories, 1), dtype=torch.int32,
+                                    device=dev),
+        "t_energy": torch.zeros(max(n_histories, 1), dtype=torch.float64,
+                                device=dev),
+        "t_fate": torch.zeros(max(n_histories, 1), dtype=torch.uint8,
+                              device=dev),
+    }
+    b = xs_event_buffers(*[buf[f].data_ptr() for f, _ in
+                           xs_event_buffers._fields_])
+    cfg = xs_event_config(n_slots, n_histories, seed, e_cut, check_every,
+                          max_iterations)
+    pp = ctypes.byref(params) if params is not None else None
+    lib = load_library()
+    if workspace is None:
+        nb = ctypes.c_size_t()
+        _check(lib.xs_event_workspace_size(tables.handle, ctypes.byref(cfg), pp,
+                                           ctypes.byref(nb)),
+               "xs_event_workspace_size")
+        keep, ws, nb = _workspace(nb.value, dev)
+    else:
+        keep, ws, nb = workspace
+    r = xs_event_result()
+    _check(lib.xs_event_run(tables.handle, ctypes.byref(cfg), ctypes.byref(b),
+                            pp, ws, nb, _stream_ptr(stream, dev),
+                            ctypes.byref(r)), "xs_event_run")
+    res = {f: getattr(r, f) for f, _ in xs_event_result._fields_}
+    tallies = {"collisions": buf["t_collisions"][:n_histories],
+               "energy": buf["t_energy"][:n_histories],
+               "fate": buf["t_fate"][:n_histories]}
+    return res, tallies

@@ -33,31 +33,36 @@ def test_exports_every_declared_function(lib):
     assert set(names) <= exported
 
 
+STRUCTS = ["xs_table_desc", "xs_params", "xs_table_info_t", "xs_profile_t",
+           "xs_tune_config", "xs_tune_result", "xs_request",
+           "xs_request_stats", "xs_event_config", "xs_event_buffers",
+           "xs_event_result"]
+
+
 def test_struct_layouts_match_header(tmp_path):
+    """Size and every field offset of each struct the binding declares equal
+    what a C compiler makes of include/xs.h."""
+    lines = []
+    for name in STRUCTS:
+        cls = getattr(xs, name)
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
     src = tmp_path / "layout.c"
-    src.write_text(r'''
-#include <stdio.h>
-#include <stddef.h>
-#include "xs.h"
-int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(xs_table_desc), sizeof(xs_params),
-         sizeof(xs_table_info_t), sizeof(xs_profile_t));
-  printf("%zu %zu %zu\n", offsetof(xs_table_desc, n_hash_bins),
-         offsetof(xs_params, sort_threshold), offsetof(xs_table_info_t, e_min));
-  return 0;
-}
-''')
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"xs.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) +
+                   "\n  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"),
                     "-o", str(exe), str(src)], check=True)
-    sizes, offs = subprocess.run([str(exe)], capture_output=True, text=True,
-                                 check=True).stdout.split("\n")[:2]
-    assert [int(v) for v in sizes.split()] == [
-        ctypes.sizeof(xs.xs_table_desc), ctypes.sizeof(xs.xs_params),
-        ctypes.sizeof(xs.xs_table_info_t), ctypes.sizeof(xs.xs_profile_t)]
-    assert [int(v) for v in offs.split()] == [
-        xs.xs_table_desc.n_hash_bins.offset, xs.xs_params.sort_threshold.offset,
-        xs.xs_table_info_t.e_min.offset]
+    out = subprocess.run([str(exe)], capture_output=True, text=True,
+                         check=True).stdout.splitlines()
+    got = {tuple(l.split()[:-1]): int(l.split()[-1]) for l in out}
+    for name in STRUCTS:
+        cls = getattr(xs, name)
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
 
 
 def test_status_strings(lib):
