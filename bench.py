@@ -28,6 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# Vector ALU issue for the lookup's arithmetic: 256 compute units x 64 lanes
+# x 2.4 GHz = 39.3e12 operations/s.  The vendor's 157.3 TFLOP/s (FP32) counts
+# packed two-wide FMAs and 78.6 (FP64) FMAs; the lookup may use neither (its
+# products and sums must round separately to stay exact, and packed FP32 code
+# generation is off), so each operation is one flop at one lane-issue.
+ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 METRIC = ("macro-XS lookups/s (FP64 plain vs FP32 autotuned) + % HBM "
           "roofline, 1 MI355X")
 
@@ -46,6 +52,46 @@ def bytes_per_lookup(precision: int, nbar: float) -> float:
     if precision == 0:
         return 52.0 + 108.0 * nbar
     return 32.0 + 64.0 * nbar
+
+
+def flops_per_pair(precision: int) -> float:
+    """Algorithmic floating-point operations per (lookup, nuclide): 3
+    subtractions, 1 division, 10 multiplications and 5 additions to
+    interpolate, 5 multiplications and 5 additions to accumulate (29); the
+    FP32 form adds 15 for the Kahan compensation (44)."""
+    return 29.0 if precision == 0 else 44.0
+
+
+def roofline(n: int, nbar: float, precision: int, kernel_ms: float,
+             traffic) -> dict:
+    """Roofline of one lookup kernel.  Two ceilings apply: HBM bandwidth
+    against the algorithmic bytes, and vector ALU issue against the
+    algorithmic flops.  Sorted and LDS-staged lookups serve most of their
+    bytes from caches (demand above the HBM peak), so the bound is the ALU
+    one when the measured fabric traffic (or, without a measurement, the
+    demand rate) leaves it the larger fraction."""
+    sec = kernel_ms * 1e-3
+    B = bytes_per_lookup(precision, nbar)
+    hbm_ach = n * B / sec / 1e9
+    F = flops_per_pair(precision)
+    alu_ach = n * nbar * F / sec / 1e12
+    alu_frac = alu_ach / ALU_PEAK_TFLOPS
+    hbm = {"achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": hbm_ach / HBM_PEAK_GBS, "bytes_per_lookup": B}
+    alu = {"achieved": alu_ach, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": alu_frac, "flops_per_pair": F, "pairs": n * nbar}
+    if traffic is not None:
+        hbm["measured_gbs"] = traffic / sec / 1e9
+        hbm["measured_frac"] = hbm["measured_gbs"] / HBM_PEAK_GBS
+        mem_frac = hbm["measured_frac"]
+    else:
+        mem_frac = hbm["frac"] if hbm["frac"] <= 1.0 else 0.0
+    main = alu if alu_frac >= mem_frac else hbm
+    out = {"bound": "alu" if main is alu else "hbm",
+           "achieved": main["achieved"], "peak": main["peak"],
+           "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
+           "kernel_ms": kernel_ms, "hbm": hbm, "alu": alu}
+    return out
 
 
 def lookup_sources_hash() -> str:
@@ -649,20 +695,13 @@ def main(argv=None):
         fn = runner(params)
         sec = time_steps(fn, args.steps, args.warmup)
         kt = kernel_time(xs, h, fn, max(args.steps, 3))
-        B = bytes_per_lookup(params.precision, nbar)
-        achieved = n * B / (kt["ms_lookup"] * 1e-3) / 1e9
         kname = kernel_name(params)
         traffic = measured_traffic(kname, params.block_size, n)
+        rl = roofline(n, nbar, params.precision, kt["ms_lookup"], traffic)
+        rl["kernel"] = kname
         return {
             "value": n / sec, "ms_per_step": sec * 1e3,
-            "params": params.as_dict(), "kernel_ms": kt,
-            "roofline": {"bound": "hbm", "achieved": achieved,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": traffic,
-                         "kernel": kname,
-                         "kernel_ms": kt["ms_lookup"],
-                         "bytes_per_lookup": B},
+            "params": params.as_dict(), "kernel_ms": kt, "roofline": rl,
         }
 
     plain = tuned = None

@@ -102,7 +102,8 @@ typedef struct xs_tables_s* xs_tables_t;
  *  - 1 <= n_nuclides; n_channels == 5;
  *  - grid_offsets[0] == 0, n_k = grid_offsets[k+1] - grid_offsets[k] >= 2,
  *    total points < 2^31;
- *  - energy: finite, > 0 and strictly increasing within each nuclide;
+ *  - energy: within [2^-400, 2^400] (about 3.9e-121 to 2.6e120; any unit
+ *    of energy in use fits) and strictly increasing within each nuclide;
  *  - xs: [total points][5] point-major, finite and >= 0;
  *  - 1 <= n_materials <= 65536; mat_offsets[0] == 0, sizes L_m >= 1;
  *  - mat_nuclides: ids in [0, n_nuclides), no id twice within a material,

@@ -118,9 +118,11 @@ xs_status validate_desc(const xs_table_desc* d) {
       return fail(XS_ETABLE, "more than 2^31-2 grid points in total");
     for (int64_t p = a; p < b; ++p) {
       const double e = d->energy[p];
-      if (!std::isfinite(e) || !(e > 0.0))
-        return fail(XS_ETABLE, "nuclide %d point %lld: energy %g not finite "
-                    "and > 0", k, (long long)(p - a), e);
+      // [2^-400, 2^400] keeps every bracket's fraction inside the range the
+      // kernels' division handles without rescaling.
+      if (!(e >= 0x1p-400 && e <= 0x1p400))
+        return fail(XS_ETABLE, "nuclide %d point %lld: energy %g outside "
+                    "[2^-400, 2^400]", k, (long long)(p - a), e);
       if (p > a && !(d->energy[p - 1] < e))
         return fail(XS_ETABLE, "nuclide %d: energies not strictly increasing "
                     "at point %lld", k, (long long)(p - a));

@@ -223,13 +223,45 @@ struct Window {
   }
 };
 
+// max / min of two FP64 values that are never NaN (validated energies and
+// table energies), one instruction each.  The compiler's fmax/fmin would
+// first quiet each operand, which no value here needs.
+__device__ __forceinline__ double max_nonnan(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ double min_nonnan(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Correctly rounded n / d for the operands a lookup can produce from tables
+// whose energies lie in [2^-400, 2^400] (checked at table creation): d is a
+// positive difference of two such energies, so d is in [2^-452, 2^401], and
+// n is 0 or in [2^-452, d].  This is the division the compiler emits (a
+// reciprocal refined by two Newton steps, the quotient and one residual
+// correction) without its range scaling and special-case fix-up, which never
+// act on such operands (no exponent near the limits, no zero, infinity, NaN
+// or subnormal divisor): the result is the same correctly rounded quotient.
+__device__ __forceinline__ double div_in_range(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  const double q = n * r;
+  const double rem = __builtin_fma(-d, q, n);
+  return __builtin_fma(rem, r, q);
+}
+
 // Clamped energy and fraction.  min(max(E, E_k[0]), E_k[n-1]) equals
 // min(max(E, E_k[i]), E_k[i+1]) for the bracket i, so only the bracket's
 // own energies are needed.
 __device__ __forceinline__ double fraction(double e, double e0, double e1) {
-  double eh = e < e0 ? e0 : e;
-  eh = eh > e1 ? e1 : eh;
-  return (eh - e0) / (e1 - e0);
+  const double eh = min_nonnan(max_nonnan(e, e0), e1);
+  return div_in_range(eh - e0, e1 - e0);
 }
 
 // ---- accumulators and output per precision --------------------------------
@@ -678,16 +710,18 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
       const int j = jg + i;
       const MatRec r = ld_const(t.mrec + j);
       const auto rho = Acc<PREC>::rho(t, r, j);
+      R lo, hi;
       if (s_first[i] >= 0) {
-        // largest p in [0, width-2] with win[p].e <= e, else 0
-        const R* win = stage + i * kLdsW;
-        int p = 0, len = s_width[i] - 1;
+        // the record p in [0, width-2] with the largest win[p].e <= e, else 0
+        const R* q = stage + i * kLdsW;
+        int len = s_width[i] - 1;
         while (len > 1) {
           const int half = len >> 1;
-          p = (win[p + half].e <= e) ? p + half : p;
+          q = (q[half].e <= e) ? q + half : q;
           len -= half;
         }
-        acc.add(win[p], win[p + 1], e, rho);
+        lo = q[0];
+        hi = q[1];
       } else {
         if (!have_loc) {
           loc.init(t, e, mb);
@@ -696,10 +730,9 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
         const int cand = loc.start(t, r, j, e);
         Window<GRID, PREC> win;
         win.load(t, r, cand);
-        R lo, hi;
         win.finish(t, r, loc, cand, e, lo, hi);
-        acc.add(lo, hi, e, rho);
       }
+      acc.add(lo, hi, e, rho);  // one copy of the arithmetic for both paths
     }
     __syncthreads();  // the stage and window tables are rewritten next group
   }

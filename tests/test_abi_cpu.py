@@ -117,6 +117,8 @@ BAD_TABLES = {
     "energy_nan": dict(energy=_set(2, np.nan)),
     "energy_negative": dict(energy=_set(0, -1.0)),
     "energy_zero": dict(energy=_set(0, 0.0)),
+    "energy_below_range": dict(energy=_set(0, 2.0 ** -401)),
+    "energy_above_range": dict(energy=_set(-1, 2.0 ** 401)),
     "xs_negative": dict(xs=_set(7, -0.5)),
     "xs_inf": dict(xs=_set(3, np.inf)),
     "density_zero": dict(mat_density=_set(0, 0.0)),
