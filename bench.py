@@ -375,6 +375,11 @@ def tuner_study(args, torch, synth, xs):
     log(f"exhaustive: {ex.space_size} configurations in {wall:.1f} s, "
         f"optimum {opt:.3f} ms {ex.best.as_dict()}")
 
+    if args.study_table:
+        with open(args.study_table, "w") as fh:
+            json.dump({"n_lookups": n, "keys": list(keyf),
+                       "rows": [list(k) + [v] for k, v in table.items()]}, fh)
+
     def replay(p, cutoff):
         return table[tuple(getattr(p, f) for f in keyf)]
 
@@ -427,9 +432,9 @@ def energy_study(args, torch, synth, xs):
     """Run time, energy and energy-delay product of the full-size lookup
     (the paper's three objectives, section 7).  The FP32 form is tuned three
     times with the forest search, once per objective, each evaluation
-    running the batch for >= 0.15 s between two readings of the board's
-    energy accumulator; the three winners and the plain FP64 form are then
-    measured over >= 1 s each."""
+    taking the board power over >= 0.25 s of back-to-back batches (between
+    two steps of the energy accumulator) times the batch's run time; the
+    three winners and the plain FP64 form are then measured over >= 1 s."""
     from paper_2402_09222_amd.energy import EnergyMeter, measure
     meter = EnergyMeter(0)
     t = synth.config2_tables()
@@ -457,7 +462,7 @@ def energy_study(args, torch, synth, xs):
         log(f"energy study: tuning for {name}")
 
         def evaluate(p, cutoff, f=f):
-            sec, joule = measure(call(p), meter, min_seconds=0.15)
+            sec, joule, _ = measure(call(p), meter, min_seconds=0.25)
             return f(sec, joule)
         r = xs.xs_tune_search(7, xs.xs_tune_config_default(
             precision=xs.XS_FP32, strategy=xs.XS_TUNE_FOREST,
@@ -470,7 +475,7 @@ def energy_study(args, torch, synth, xs):
     for label, p in [("plain_fp64", plain)] + [(f"fp32_best_{k}", v)
                                                for k, v in winners.items()]:
         p = xs.xs_resolve_params(h, n, p)
-        sec, joule = measure(call(p), meter, min_seconds=1.0)
+        sec, joule, _ = measure(call(p), meter, min_seconds=1.0)
         rows[label] = {"params": p.as_dict(), "ms": sec * 1e3,
                        "joules": joule, "watts": joule / sec,
                        "nj_per_lookup": joule / n * 1e9,
@@ -599,7 +604,7 @@ def main(argv=None):
                     help="skip the 5.7 GB unionized index table")
     ap.add_argument("--params", type=str, default=None,
                     help="JSON dict of FP32 params instead of tuning")
-    ap.add_argument("--tune-evals", type=int, default=48,
+    ap.add_argument("--tune-evals", type=int, default=96,
                     help="evaluation budget of the forest-surrogate tuner")
     ap.add_argument("--tune-strategy", choices=["forest", "exhaustive"],
                     default="forest")
@@ -614,6 +619,8 @@ def main(argv=None):
                          "tuning space (evaluations to the optimum)")
     ap.add_argument("--study-n", type=int, default=4_000_000)
     ap.add_argument("--study-seeds", type=int, default=20)
+    ap.add_argument("--study-table", type=str, default=None,
+                    help="also write every measured configuration here")
     ap.add_argument("--event", action="store_true",
                     help="toy event loop: histories/s, queued vs queueless, "
                          "sorted vs unsorted")

@@ -90,6 +90,33 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
   return out;
 }
 
+// Categorical dimensions of a candidate for the initial design: grid, sort,
+// block size, lookups per lane, nuclides in flight, LDS staging.
+constexpr int kDesignDims = 6;
+
+int design_level(const xs_params& p, int d) {
+  switch (d) {
+    case 0: return p.grid;
+    case 1: return p.sort;
+    case 2: return p.block_size;
+    case 3: return p.lookups_per_thread;
+    case 4: return p.unroll;
+    default: return p.lds_stage;
+  }
+}
+
+std::vector<std::vector<int>> design_levels(const std::vector<Cand>& space) {
+  std::vector<std::vector<int>> lv(kDesignDims);
+  for (const Cand& c : space)
+    for (int d = 0; d < kDesignDims; ++d) {
+      const int v = design_level(c.p, d);
+      if (std::find(lv[d].begin(), lv[d].end(), v) == lv[d].end())
+        lv[d].push_back(v);
+    }
+  for (auto& l : lv) std::sort(l.begin(), l.end());
+  return lv;
+}
+
 // ---- random numbers (SplitMix64) -------------------------------------------
 
 struct Rng {
@@ -338,17 +365,41 @@ xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
       if (std::isnan(S.obj[i]))
         if (xs_status st = S.run_one(i)) return st;
   } else {
-    // Initial random configurations, then surrogate-guided batches.
+    // Initial design, then surrogate-guided batches.  The initial
+    // configurations form a Latin-hypercube draw over the categorical
+    // dimensions (grid, sort, block, lookups per lane, nuclides in flight,
+    // LDS staging): each dimension's levels are dealt out in a random order
+    // so every level appears about equally often, and sample i takes the
+    // unevaluated configuration that matches the most of its dealt levels
+    // (ties at random).  A purely random draw of ten from ~750 often misses a
+    // whole level (LDS staging is 10 % of the space), and a forest never
+    // learns what a level it has not seen is worth.
     const int init = std::max(1, std::min(cfg->init_samples, budget));
-    while ((int)S.order.size() < init) {
-      const int c = (int)rng.below(N);
-      if (!std::isnan(S.obj[c])) {
-        bool left = false;
-        for (int i = 0; i < N; ++i) left = left || std::isnan(S.obj[i]);
-        if (!left) break;
-        continue;
+    const std::vector<std::vector<int>> levels = design_levels(S.space);
+    std::vector<std::vector<int>> deal(levels.size());
+    for (size_t d = 0; d < levels.size(); ++d) {
+      deal[d] = levels[d];
+      for (size_t i = deal[d].size(); i > 1; --i)
+        std::swap(deal[d][i - 1], deal[d][rng.below(i)]);
+    }
+    for (int k = 0; (int)S.order.size() < init; ++k) {
+      int best = -1, best_match = -1;
+      uint64_t best_tie = 0;
+      for (int i = 0; i < N; ++i) {
+        if (!std::isnan(S.obj[i])) continue;
+        int match = 0;
+        for (size_t d = 0; d < levels.size(); ++d)
+          match += design_level(S.space[i].p, (int)d) ==
+                   deal[d][k % deal[d].size()];
+        const uint64_t tie = rng.next();
+        if (match > best_match || (match == best_match && tie < best_tie)) {
+          best = i;
+          best_match = match;
+          best_tie = tie;
+        }
       }
-      if (xs_status st = S.run_one(c)) return st;
+      if (best < 0) break;
+      if (xs_status st = S.run_one(best)) return st;
     }
     const int batch = std::max(1, cfg->batch);
     while ((int)S.order.size() < budget) {

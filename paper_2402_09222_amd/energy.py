@@ -58,27 +58,77 @@ class EnergyMeter:
 
 
 def measure(fn, meter: EnergyMeter, min_seconds: float = 0.25,
-            max_calls: int = 100000):
-    """Runs fn() repeatedly for at least min_seconds of device time (the
-    accumulator advances in coarse steps) and returns (seconds per call,
-    joules per call).  fn must enqueue device work on torch's current
-    stream."""
+            depth: int = 4):
+    """Board power while fn() runs back to back, and the energy of one call.
+
+    The accumulator advances in steps at the firmware's update period, so a
+    window between two arbitrary readings is off by up to one step.  Here
+    the device is kept busy (up to `depth` calls queued) and the accumulator
+    is polled while waiting; the window runs from one observed step to the
+    first step after at least min_seconds, and power = energy difference /
+    time between those two steps (the accumulator's own timestamps when
+    they advance with it, else the host clock at detection).  The time of a
+    call is measured on its own (synchronised wall time over several calls),
+    and joules per call = power x seconds per call.
+
+    fn must enqueue device work on torch's current stream.  Returns
+    (seconds per call, joules per call, watts)."""
     import time
 
     import torch
     fn()
     torch.cuda.synchronize()
+    # seconds per call
     t0 = time.perf_counter()
     fn()
     torch.cuda.synchronize()
     one = max(time.perf_counter() - t0, 1e-6)
-    calls = int(min(max_calls, max(3, min_seconds / one)))
-    torch.cuda.synchronize()
-    j0 = meter.joules()
+    reps = int(max(3, min(1000, 0.05 / one)))
     t0 = time.perf_counter()
-    for _ in range(calls):
+    for _ in range(reps):
         fn()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    j1 = meter.joules()
-    return dt / calls, (j1 - j0) / calls
+    sec = (time.perf_counter() - t0) / reps
+
+    def reading():
+        e = meter._smi.amdsmi_get_energy_count(meter.handle)
+        return (e["energy_accumulator"] * e["counter_resolution"] * 1e-6,
+                e["timestamp"], time.perf_counter())
+
+    events = []
+    marks = []  # readings just after the accumulator stepped
+    last = reading()
+    deadline = None
+    limit = time.perf_counter() + 20.0 * max(min_seconds, 10 * one) + 5.0
+    while True:
+        ev = torch.cuda.Event()
+        fn()
+        ev.record()
+        events.append(ev)
+        while len(events) >= depth and not events[0].query():
+            r = reading()
+            if r[0] != last[0]:
+                if len(marks) == 0 or (deadline and r[2] >= deadline):
+                    marks.append(r)
+                    if len(marks) == 1:
+                        deadline = r[2] + min_seconds
+                last = r
+        while len(events) >= depth and events[0].query():
+            events.pop(0)
+        if len(marks) >= 2:
+            break
+        if time.perf_counter() > limit:
+            torch.cuda.synchronize()
+            raise RuntimeError("the energy accumulator did not advance")
+    torch.cuda.synchronize()
+    (e0, ts0, h0), (e1, ts1, h1) = marks[0], marks[1]
+    dt = h1 - h0
+    if ts1 > ts0:
+        # the accumulator's timestamp: pick the power of ten that matches
+        # the host clock
+        import math
+        unit = 10.0 ** round(math.log10((ts1 - ts0) / dt))
+        if abs((ts1 - ts0) / unit - dt) < 0.2 * dt:
+            dt = (ts1 - ts0) / unit
+    watts = (e1 - e0) / dt
+    return sec, watts * sec, watts
