@@ -139,11 +139,14 @@ typedef struct {
   int32_t sort;               /* XS_SORT_* */
   int32_t block_size;         /* 64..1024, multiple of 64; with
                                  w = lookups_per_thread * unroll, at most 512
-                                 when w > 2 and 256 when w > 4 */
+                                 when w > 2 and 256 when w > 4; with
+                                 lds_stage = 1 at most 1024 /
+                                 lookups_per_thread */
   int32_t lookups_per_thread; /* 1..8 */
   int32_t lds_stage;          /* 1: blocks whose lookups share a material
                                  stage each nuclide's bracket window in LDS
-                                 (needs lookups_per_thread = unroll = 1) */
+                                 (needs lookups_per_thread <= 2 and
+                                 unroll = 1) */
   int64_t sort_threshold;     /* sort only when n >= sort_threshold
                                  (0 = always, INT64_MAX = never) */
   int32_t queue;              /* xs_lookup_active only: XS_QUEUE_* */

@@ -233,9 +233,10 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
                 p.lookups_per_thread);
   if (p.lds_stage != 0 && p.lds_stage != 1)
     return fail(XS_EINVAL, "lds_stage must be 0 or 1");
-  if (p.lds_stage == 1 && (p.lookups_per_thread != 1 || p.unroll != 1))
-    return fail(XS_EINVAL, "lds_stage = 1 runs one lookup per lane with one "
-                "nuclide in flight (lookups_per_thread = unroll = 1)");
+  if (p.lds_stage == 1 && (p.lookups_per_thread > 2 || p.unroll != 1))
+    return fail(XS_EINVAL, "lds_stage = 1 runs one or two lookups per lane "
+                "with one nuclide in flight (lookups_per_thread <= 2, "
+                "unroll = 1)");
   if (p.queue != XS_QUEUE_COMPACT && p.queue != XS_QUEUE_PREDICATED)
     return fail(XS_EINVAL, "unknown queue mode %d", p.queue);
   if (p.unroll != 1 && p.unroll != 2 && p.unroll != 4)
@@ -245,7 +246,9 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
                 p.unroll);
   {
     const int w = p.lookups_per_thread * p.unroll;
-    const int max_block = w <= 2 ? 1024 : (w <= 4 ? 512 : 256);
+    const int max_block = p.lds_stage == 1
+                              ? 1024 / p.lookups_per_thread
+                              : (w <= 2 ? 1024 : (w <= 4 ? 512 : 256));
     if (p.block_size > max_block)
       return fail(XS_EINVAL, "block_size %d too large for %d lookups per lane "
                   "x %d nuclides in flight (max %d)", p.block_size,

@@ -600,9 +600,9 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 constexpr int kLdsW = 8;       // records per staged window
 constexpr int kLdsGroup = 32;  // nuclides per staging round
 
-template <int GRID, int PREC>
-__global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
-                                                     const LookupArgs a) {
+template <int GRID, int PREC, int LPT>
+__global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
+                                                           const LookupArgs a) {
   using R = typename RecOf<PREC>::T;
   __shared__ R stage[kLdsGroup * kLdsW];
   __shared__ int s_first[kLdsGroup];  // first staged record, or -1: per lane
@@ -613,45 +613,64 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
   const int tid = threadIdx.x;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t n = a.count_dev ? *a.count_dev : a.n;
-  const int64_t q = blk * (int64_t)blockDim.x + tid;
+  const int64_t first = blk * (int64_t)blockDim.x * LPT + tid;
 
-  bool act = q < n;
-  int64_t o = 0;
-  double e = 1.0;
-  int m = -1;
-  if (act) {
-    o = a.perm ? (int64_t)a.perm[q] : q;
-    if ((uint64_t)o >= (uint64_t)a.n) act = false;
-    else if (a.active && !a.active[o]) act = false;
-  }
-  if (act) {
-    e = a.E[o];
-    m = a.mat[o];
-    if (!valid_query(e, m, t.M)) {
-      Acc<PREC>::store_nan(a.out, o);
-      act = false;
+  // Lane tid takes queue positions first, first + blockDim, ... (coalesced).
+  bool act[LPT];
+  int64_t o[LPT];
+  double e[LPT];
+  int m[LPT];
+#pragma unroll
+  for (int l = 0; l < LPT; ++l) {
+    const int64_t q = first + (int64_t)l * blockDim.x;
+    act[l] = q < n;
+    o[l] = 0;
+    e[l] = 1.0;
+    m[l] = -1;
+    if (act[l]) {
+      o[l] = a.perm ? (int64_t)a.perm[q] : q;
+      if ((uint64_t)o[l] >= (uint64_t)a.n) act[l] = false;
+      else if (a.active && !a.active[o[l]]) act[l] = false;
+    }
+    if (act[l]) {
+      e[l] = a.E[o[l]];
+      m[l] = a.mat[o[l]];
+      if (!valid_query(e[l], m[l], t.M)) {
+        Acc<PREC>::store_nan(a.out, o[l]);
+        act[l] = false;
+      }
     }
   }
-  if (tid == 0) s_mat = act ? m : -1;
+  if (tid == 0) s_mat = act[0] ? m[0] : -1;
   __syncthreads();
   const int mb = s_mat;
-  const bool uniform = __syncthreads_and(act && m == mb && mb >= 0);
+  bool mine = mb >= 0;
+#pragma unroll
+  for (int l = 0; l < LPT; ++l) mine = mine && act[l] && m[l] == mb;
+  const bool uniform = __syncthreads_and(mine);
 
   if (!uniform) {
-    if (act) {
-      const double e1[1] = {e};
+#pragma unroll
+    for (int l = 0; l < LPT; ++l) {
+      if (!act[l]) continue;
+      const double e1[1] = {e[l]};
       Locator<GRID> l1[1];
       Acc<PREC> a1[1];
-      l1[0].init(t, e, m);
+      l1[0].init(t, e[l], m[l]);
       a1[0].zero();
-      walk_material<GRID, PREC, 1, 1>(t, m, e1, l1, a1);
-      a1[0].store(a.out, o);
+      walk_material<GRID, PREC, 1, 1>(t, m[l], e1, l1, a1);
+      a1[0].store(a.out, o[l]);
     }
     return;
   }
 
-  // Block energy range (all lanes active here).
-  double lo_e = e, hi_e = e;
+  // Block energy range (all lookups of the block are active here).
+  double lo_e = e[0], hi_e = e[0];
+#pragma unroll
+  for (int l = 1; l < LPT; ++l) {
+    lo_e = fmin(lo_e, e[l]);
+    hi_e = fmax(hi_e, e[l]);
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     lo_e = fmin(lo_e, __shfl_xor(lo_e, off, 64));
@@ -683,10 +702,11 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
     edge_hi.init(t, hi_e, mb);
   }
 
-  Locator<GRID> loc;  // this lane's own search state, made on first need
+  Locator<GRID> loc[LPT];  // this lane's own search states, made on first need
   bool have_loc = false;
-  Acc<PREC> acc;
-  acc.zero();
+  Acc<PREC> acc[LPT];
+#pragma unroll
+  for (int l = 0; l < LPT; ++l) acc[l].zero();
   const R* recs = RecOf<PREC>::base(t);
   const int j0 = ld_const(t.moff + mb), j1 = ld_const(t.moff + mb + 1);
   for (int jg = j0; jg < j1; jg += kLdsGroup) {
@@ -702,41 +722,56 @@ __global__ __launch_bounds__(1024) void k_lookup_lds(const DevTables t,
     __syncthreads();
     for (int s = tid; s < cnt * kLdsW; s += blockDim.x) {
       const int i = s / kLdsW, k = s % kLdsW;
-      const int first = s_first[i];
-      if (first >= 0 && k < s_width[i]) stage[s] = recs[first + k];
+      const int first_rec = s_first[i];
+      if (first_rec >= 0 && k < s_width[i]) stage[s] = recs[first_rec + k];
     }
     __syncthreads();
     for (int i = 0; i < cnt; ++i) {
       const int j = jg + i;
       const MatRec r = ld_const(t.mrec + j);
       const auto rho = Acc<PREC>::rho(t, r, j);
-      R lo, hi;
+      R lo[LPT], hi[LPT];
       if (s_first[i] >= 0) {
-        // the record p in [0, width-2] with the largest win[p].e <= e, else 0
-        const R* q = stage + i * kLdsW;
+        // the record p in [0, width-2] with the largest win[p].e <= e,
+        // else 0; the LPT searches run in lock step
+        const R* q[LPT];
+#pragma unroll
+        for (int l = 0; l < LPT; ++l) q[l] = stage + i * kLdsW;
         int len = s_width[i] - 1;
         while (len > 1) {
           const int half = len >> 1;
-          q = (q[half].e <= e) ? q + half : q;
+#pragma unroll
+          for (int l = 0; l < LPT; ++l)
+            q[l] = (q[l][half].e <= e[l]) ? q[l] + half : q[l];
           len -= half;
         }
-        lo = q[0];
-        hi = q[1];
+#pragma unroll
+        for (int l = 0; l < LPT; ++l) {
+          lo[l] = q[l][0];
+          hi[l] = q[l][1];
+        }
       } else {
         if (!have_loc) {
-          loc.init(t, e, mb);
+#pragma unroll
+          for (int l = 0; l < LPT; ++l) loc[l].init(t, e[l], mb);
           have_loc = true;
         }
-        const int cand = loc.start(t, r, j, e);
-        Window<GRID, PREC> win;
-        win.load(t, r, cand);
-        win.finish(t, r, loc, cand, e, lo, hi);
+#pragma unroll
+        for (int l = 0; l < LPT; ++l) {
+          const int cand = loc[l].start(t, r, j, e[l]);
+          Window<GRID, PREC> win;
+          win.load(t, r, cand);
+          win.finish(t, r, loc[l], cand, e[l], lo[l], hi[l]);
+        }
       }
-      acc.add(lo, hi, e, rho);  // one copy of the arithmetic for both paths
+      // one copy of the arithmetic for both paths
+#pragma unroll
+      for (int l = 0; l < LPT; ++l) acc[l].add(lo[l], hi[l], e[l], rho);
     }
     __syncthreads();  // the stage and window tables are rewritten next group
   }
-  acc.store(a.out, o);
+#pragma unroll
+  for (int l = 0; l < LPT; ++l) acc[l].store(a.out, o[l]);
 }
 
 // ---- launchers ------------------------------------------------------------------
@@ -776,16 +811,22 @@ template <int GRID>
 hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
                               const LookupArgs& a, hipStream_t s) {
   if (p.lds_stage) {
-    if (p.lookups_per_thread != 1 || p.unroll != 1) return hipErrorInvalidValue;
-    const int64_t nb = (a.n + p.block_size - 1) / p.block_size;
+    const int lpt = p.lookups_per_thread;
+    if ((lpt != 1 && lpt != 2) || p.unroll != 1 ||
+        p.block_size > 1024 / lpt)
+      return hipErrorInvalidValue;
+    const int64_t per_block = (int64_t)p.block_size * lpt;
+    const int64_t nb = (a.n + per_block - 1) / per_block;
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    if (p.precision == XS_FP64)
-      hipLaunchKernelGGL((k_lookup_lds<GRID, XS_FP64>), dim3((unsigned)nb),
-                         dim3(p.block_size), 0, s, t, a);
-    else
-      hipLaunchKernelGGL((k_lookup_lds<GRID, XS_FP32>), dim3((unsigned)nb),
-                         dim3(p.block_size), 0, s, t, a);
+    const dim3 grid((unsigned)nb), block((unsigned)p.block_size);
+#define XS_LDS(P, L) hipLaunchKernelGGL((k_lookup_lds<GRID, P, L>), grid, block, 0, s, t, a)
+    if (p.precision == XS_FP64) {
+      if (lpt == 1) XS_LDS(XS_FP64, 1); else XS_LDS(XS_FP64, 2);
+    } else {
+      if (lpt == 1) XS_LDS(XS_FP32, 1); else XS_LDS(XS_FP32, 2);
+    }
+#undef XS_LDS
     return hipGetLastError();
   }
   if (!variant_exists(p.lookups_per_thread, p.unroll) ||

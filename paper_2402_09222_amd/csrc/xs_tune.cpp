@@ -59,11 +59,13 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
     for (int s = 0; s < 5; ++s) {
       if (!(sorts >> s & 1u)) continue;
       for (int b : kBlocks) {
-        for (int vi = 0; vi <= kNumVariants; ++vi) {
-          // the last variant is LDS staging (one lookup, one nuclide per lane)
-          const bool lds = vi == kNumVariants;
-          const int v[2] = {lds ? 1 : kVariants[vi][0], lds ? 1 : kVariants[vi][1]};
-          if (b > max_block(v[0], v[1])) continue;
+        for (int vi = 0; vi < kNumVariants + 2; ++vi) {
+          // the last two variants are LDS staging with one or two lookups
+          // per lane (one nuclide in flight)
+          const bool lds = vi >= kNumVariants;
+          const int v[2] = {lds ? vi - kNumVariants + 1 : kVariants[vi][0],
+                            lds ? 1 : kVariants[vi][1]};
+          if (b > (lds ? 1024 / v[0] : max_block(v[0], v[1]))) continue;
           Cand c{};
           c.p.precision = precision;
           c.p.grid = g;

@@ -101,7 +101,9 @@ def test_fp32_samples_and_bound(full, grid):
               dict(sort="band_material", sort_threshold=0, block_size=512,
                    lookups_per_thread=2, unroll=2),
               dict(sort="band_material", sort_threshold=0, block_size=256,
-                   lookups_per_thread=1, unroll=1, lds_stage=1)):
+                   lookups_per_thread=1, unroll=1, lds_stage=1),
+              dict(sort="band_material", sort_threshold=0, block_size=128,
+                   lookups_per_thread=2, unroll=1, lds_stage=1)):
         o2 = run(full, precision=xs.XS_FP32, grid=grid, **k).cpu().numpy()
         assert np.array_equal(o2, o), k
 

@@ -118,6 +118,10 @@ KNOBS = [
          lds_stage=1),
     dict(sort="material_energy", sort_threshold=0, block_size=1024,
          lookups_per_thread=1, unroll=1, lds_stage=1),
+    dict(sort="band_material", sort_threshold=0, block_size=128,
+         lookups_per_thread=2, unroll=1, lds_stage=1),
+    dict(sort="none", block_size=512, lookups_per_thread=2, unroll=1,
+         lds_stage=1),
 ]
 
 
@@ -246,7 +250,8 @@ def test_errors_from_device_calls(cfg1):
                 dict(block_size=1024, lookups_per_thread=2, unroll=2),
                 dict(lookups_per_thread=3, unroll=2), dict(unroll=3),
                 dict(sort=5), dict(grid=3), dict(lds_stage=2),
-                dict(lds_stage=1, lookups_per_thread=2),
+                dict(lds_stage=1, lookups_per_thread=3),
+                dict(lds_stage=1, lookups_per_thread=2, block_size=1024),
                 dict(lds_stage=1, unroll=2)):
         with pytest.raises(xs.XsError) as e:
             xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
@@ -333,13 +338,16 @@ def test_lds_staging_groups(union_by_material):
         grids = ("unionized",) if union_by_material else (
             "nuclide", "hash", "unionized")
         for grid in grids:
-            for bs, sort in ((64, "band_material"), (256, "material_energy"),
-                             (1024, "band_material"), (128, "none")):
+            for bs, lpt, sort in ((64, 1, "band_material"),
+                                  (256, 1, "material_energy"),
+                                  (1024, 1, "band_material"), (128, 1, "none"),
+                                  (64, 2, "band_material"),
+                                  (512, 2, "material_energy")):
                 for prec, r in ((xs.XS_FP64, ref), (xs.XS_FP32, ref32)):
                     out = run(h, E, m, precision=prec, grid=grid, sort=sort,
                               sort_threshold=0, block_size=bs,
-                              lookups_per_thread=1, unroll=1, lds_stage=1)
-                    assert np.array_equal(out, r), (grid, bs, sort, prec)
+                              lookups_per_thread=lpt, unroll=1, lds_stage=1)
+                    assert np.array_equal(out, r), (grid, bs, lpt, sort, prec)
     finally:
         h.close()
 

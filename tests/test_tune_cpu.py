@@ -58,7 +58,8 @@ def all_valid(calls):
         assert c["u"] == 1 or c["lpt"] <= 2
         assert c["bs"] <= max_block(c["lpt"], c["u"])
         assert c["lds"] in (0, 1)
-        assert c["lds"] == 0 or (c["lpt"] == 1 and c["u"] == 1)
+        assert c["lds"] == 0 or (c["lpt"] <= 2 and c["u"] == 1 and
+                                 c["bs"] <= 1024 // c["lpt"])
         # conditional parameter: the threshold only means something when a
         # sort is selected; it is never varied within a policy
         assert c["thr"] == (INT64_MAX if c["sort"] == 0 else 0)
@@ -90,9 +91,10 @@ def cost_of(c):
 
 def test_space_size_matches_enumeration():
     n = 0
-    for lpt, u in [(l, 1) for l in range(1, 9)] + [(1, 2), (2, 2), (1, 4), (2, 4),
-                                                 (1, 1)]:  # last: LDS staging
+    for lpt, u in [(l, 1) for l in range(1, 9)] + [(1, 2), (2, 2), (1, 4), (2, 4)]:
         n += sum(1 for b in BLOCKS if b <= max_block(lpt, u))
+    for lpt in (1, 2):  # LDS staging
+        n += sum(1 for b in BLOCKS if b <= 1024 // lpt)
     for grids, mult in ((7, 3), (1, 1), (5, 2)):
         cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0)
         r = xs.xs_tune_search(grids, cfg, Recorder())
@@ -117,7 +119,7 @@ def test_timeout_rule_cuts_and_scores_at_cutoff():
 
 
 def test_forest_beats_random_search():
-    """With 40 of the 750 configurations, the surrogate-guided search lands
+    """With 40 of the ~840 configurations, the surrogate-guided search lands
     within 8% of the optimum on average over seeds and within 1.5x for every
     seed, and on average beats the best of 40 random configurations.  (Only
     a handful of configurations lie within 10% of this optimum.)"""
