@@ -139,7 +139,7 @@ typedef struct {
   int32_t sort;               /* XS_SORT_* */
   int32_t block_size;         /* 64..1024, multiple of 64; with
                                  w = lookups_per_thread * unroll, at most 512
-                                 when w > 2 and 256 when w > 4; with
+                                 when w > 1 and 256 when w > 4; with
                                  lds_stage = 1 at most 1024 /
                                  lookups_per_thread */
   int32_t lookups_per_thread; /* 1..8 */

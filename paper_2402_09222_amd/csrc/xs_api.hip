@@ -248,7 +248,7 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
     const int w = p.lookups_per_thread * p.unroll;
     const int max_block = p.lds_stage == 1
                               ? 1024 / p.lookups_per_thread
-                              : (w <= 2 ? 1024 : (w <= 4 ? 512 : 256));
+                              : (w <= 1 ? 1024 : (w <= 4 ? 512 : 256));
     if (p.block_size > max_block)
       return fail(XS_EINVAL, "block_size %d too large for %d lookups per lane "
                   "x %d nuclides in flight (max %d)", p.block_size,

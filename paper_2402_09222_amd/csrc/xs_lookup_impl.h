@@ -67,7 +67,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
 // independent chains per lane need more registers, so fewer lanes fit per
 // compute unit.
 constexpr int max_block_for(int lpt, int unroll) {
-  return lpt * unroll <= 2 ? 1024 : (lpt * unroll <= 4 ? 512 : 256);
+  return lpt * unroll <= 1 ? 1024 : (lpt * unroll <= 4 ? 512 : 256);
 }
 
 // ---- records per precision ---------------------------------------------------
@@ -176,6 +176,17 @@ struct Locator<XS_GRID_UNIONIZED> {
     return nullptr;
   }
 };
+
+// Keeps a record's fields in registers at this point: the compiler may not
+// move the loads that produced them past it (used to keep LDS reads and
+// global reads of the same record type in their own branches instead of
+// merging them into one load through a generic pointer).
+template <class R>
+__device__ __forceinline__ void pin_rec(R& r) {
+#pragma unroll
+  for (int k = 0; k < XS_CHANNELS; ++k) asm volatile("" : "+v"(r.x[k]));
+  asm volatile("" : "+v"(r.e));
+}
 
 // Field-wise out = c ? a : b.  Selecting whole records by reference would
 // make the compiler select an address and keep the records on the stack.
@@ -734,21 +745,24 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
       if (s_first[i] >= 0) {
         // the record p in [0, width-2] with the largest win[p].e <= e,
         // else 0; the LPT searches run in lock step
-        const R* q[LPT];
+        int q[LPT];  // indices into stage (kept as indices so the reads
+                     // stay LDS reads)
 #pragma unroll
-        for (int l = 0; l < LPT; ++l) q[l] = stage + i * kLdsW;
+        for (int l = 0; l < LPT; ++l) q[l] = i * kLdsW;
         int len = s_width[i] - 1;
         while (len > 1) {
           const int half = len >> 1;
 #pragma unroll
           for (int l = 0; l < LPT; ++l)
-            q[l] = (q[l][half].e <= e[l]) ? q[l] + half : q[l];
+            q[l] = (stage[q[l] + half].e <= e[l]) ? q[l] + half : q[l];
           len -= half;
         }
 #pragma unroll
         for (int l = 0; l < LPT; ++l) {
-          lo[l] = q[l][0];
-          hi[l] = q[l][1];
+          lo[l] = stage[q[l]];
+          hi[l] = stage[q[l] + 1];
+          pin_rec(lo[l]);
+          pin_rec(hi[l]);
         }
       } else {
         if (!have_loc) {

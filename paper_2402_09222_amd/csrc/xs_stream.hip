@@ -1,16 +1,18 @@
-// Request streams: many uneven lookup batches served by one persistent,
-// graph-launched kernel (xs_stream_*).
+// Many uneven lookup requests served together: xs_lookup_requests (one
+// call per batch of requests) and the request streams xs_stream_* (a
+// persistent kernel replayed from a HIP graph).
 //
 // The paper's particle buffer is refilled after every kernel call and the
 // host launches one event kernel per queue (section 5.1, "maximum number of
 // particles in-flight" and "queuing logic"); with short kernels the launch
-// and the count transfer to the host leave bubbles.  Here a batch of requests
-// is described once in device memory and a single launch drains it: each
-// block claims the next tile of 1024 lookups with an atomic counter, sorts
-// the tile in LDS by (material, energy) so that waves hold one material,
-// runs the lookup walk of the main kernel and stamps the request's first and
-// last tile times with the device wall clock.  Every block leaves its loop
-// once the counter passes the batch's tile count, so the grid always drains.
+// and the count transfer to the host leave bubbles.  Here a batch of
+// requests is described once in device memory and drained by one launch
+// (or, batch-sorted, by one gather, one sorted lookup and one scatter).  The
+// request kernels work in tiles of 1024 lookups: a block sorts its tile in
+// LDS by (material, energy) so that waves hold one material, runs the lookup
+// walk of the main kernel and stamps the request's first and last tile times
+// with the device wall clock.  Every loop bound is a kernel argument
+// computed on the host.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -43,7 +43,7 @@ struct Cand {
 
 int max_block(int lpt, int unroll) {
   const int w = lpt * unroll;
-  return w <= 2 ? 1024 : (w <= 4 ? 512 : 256);
+  return w <= 1 ? 1024 : (w <= 4 ? 512 : 256);
 }
 
 std::vector<Cand> enumerate_space(int precision, uint32_t grids,

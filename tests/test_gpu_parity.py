@@ -96,7 +96,7 @@ def test_cfg1_indices_bit_exact(cfg1, grid):
 
 KNOBS = [
     dict(sort="none", block_size=64, lookups_per_thread=1, unroll=1),
-    dict(sort="none", block_size=1024, lookups_per_thread=2, unroll=1),
+    dict(sort="none", block_size=512, lookups_per_thread=2, unroll=1),
     dict(sort="material", sort_threshold=0, block_size=128, lookups_per_thread=3),
     dict(sort="energy", sort_threshold=0, block_size=512, lookups_per_thread=4),
     dict(sort="material_energy", sort_threshold=0, block_size=256,
@@ -105,7 +105,7 @@ KNOBS = [
          lookups_per_thread=1, unroll=4),
     dict(sort="band_material", sort_threshold=0, block_size=256,
          lookups_per_thread=2, unroll=2),
-    dict(sort="none", block_size=1024, lookups_per_thread=1, unroll=2),
+    dict(sort="none", block_size=512, lookups_per_thread=1, unroll=2),
     dict(sort="material_energy", sort_threshold=xs.INT64_MAX, block_size=192,
          lookups_per_thread=5),
     dict(sort="band_material", sort_threshold=20000, block_size=64,

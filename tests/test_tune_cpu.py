@@ -21,7 +21,7 @@ BLOCKS = (64, 128, 256, 512, 1024)
 
 def max_block(lpt, unroll):
     w = lpt * unroll
-    return 1024 if w <= 2 else (512 if w <= 4 else 256)
+    return 1024 if w <= 1 else (512 if w <= 4 else 256)
 
 
 def cost(p):
