@@ -217,8 +217,13 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.lds_stage == XS_AUTO) p.lds_stage = t.lds_stage;
   if (p.sort_threshold < 0) p.sort_threshold = t.sort_threshold;
   if (p.queue == XS_AUTO) p.queue = t.queue;
-  if (p.unroll == 0 || p.unroll == XS_AUTO)
-    p.unroll = (p.lookups_per_thread <= 2 && p.lds_stage != 1) ? t.unroll : 1;
+  if (p.unroll == 0 || p.unroll == XS_AUTO) {
+    // the tuned depth when it applies and the block leaves room for it
+    const int u = (p.lookups_per_thread <= 2 && p.lds_stage != 1) ? t.unroll : 1;
+    const int w = p.lookups_per_thread * u;
+    const int max_block = w <= 1 ? 1024 : (w <= 4 ? 512 : 256);
+    p.unroll = p.block_size <= max_block ? u : 1;
+  }
 
   if (p.grid < 0 || p.grid > 2) return fail(XS_EINVAL, "unknown grid %d", p.grid);
   if (p.grid == XS_GRID_HASH && h->d.B == 0)
