@@ -189,9 +189,10 @@ def _pctl(v, q):
 
 def sweep_in_flight(args, torch, synth, xs):
     """Config 4: batches of 1e5 ... 8e6 lookups on the full-size tables; per
-    batch size the FP32 form is tuned (forest search) and timed, beside the
-    plain FP64 lookup and the FP32 form under each sort policy at the tuned
-    launch shape.  One JSON line per batch size."""
+    batch size the FP32 form is tuned (forest search) and timed, eagerly and
+    as one captured HIP graph replayed (no launch overhead per kernel),
+    beside the plain FP64 lookup and the FP32 form under each sort policy at
+    the tuned launch shape.  One JSON line per batch size."""
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
              xs.XS_BUILD_UNION_BY_MATERIAL)
@@ -217,8 +218,25 @@ def sweep_in_flight(args, torch, synth, xs):
                                         max_evals=args.tune_evals, reps=3)
         r = xs.xs_tune(h, E, m, cfg, workspace=ws)
         best = r.best
+        def graph_rate(p):
+            """The same call captured once in a HIP graph and replayed."""
+            out = torch.empty((n, 5), device="cuda:0", dtype=torch.float64
+                              if p.precision == 0 else torch.float32)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                xs.xs_lookup_batch(h, E, m, out=out, params=p, workspace=ws)
+            torch.cuda.current_stream().wait_stream(side)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                xs.xs_lookup_batch(h, E, m, out=out, params=p, workspace=ws)
+            sec = time_steps(g.replay, args.steps, args.warmup)
+            del g
+            return n / sec
+
         row = {"n": n, "mean_nuclides": nbar, "tuned": best.as_dict(),
                "tuned_lookups_per_s": rate(best),
+               "tuned_graph_lookups_per_s": graph_rate(best),
                "tuner": {"evaluated": r.evaluated, "cut": r.cut,
                          "best_eval": r.best_eval}}
         plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
