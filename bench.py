@@ -95,11 +95,17 @@ def roofline(n: int, nbar: float, precision: int, kernel_ms: float,
 
 
 def lookup_sources_hash() -> str:
+    """Hash of the lookup kernels' code (comments and blank space removed,
+    so a comment edit does not orphan measured counters)."""
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2402_09222_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.startswith("xs_lookup") or f == "xs_internal.h":
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            text = open(os.path.join(csrc, f)).read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -495,6 +501,7 @@ def energy_study(args, torch, synth, xs):
         p = xs.xs_resolve_params(h, n, p)
         sec, joule, _ = measure(call(p), meter, min_seconds=1.0)
         rows[label] = {"params": p.as_dict(), "ms": sec * 1e3,
+                       "window": dict(measure.last),
                        "joules": joule, "watts": joule / sec,
                        "nj_per_lookup": joule / n * 1e9,
                        "edp_js": joule * sec,

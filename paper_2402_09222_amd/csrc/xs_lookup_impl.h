@@ -606,7 +606,9 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 // holding several materials (or a partial last block) takes the per-lane
 // walk.  Same arithmetic, same order: the sums are bit-identical to
 // k_lookup's.  Three barriers per group of nuclides instead of a search and
-// a window load per (lookup, nuclide).
+// a window load per (lookup, nuclide).  Each lane handles LPT (1 or 2)
+// lookups; the block's energy range covers all of them and their in-LDS
+// searches run in lock step.
 
 constexpr int kLdsW = 8;       // records per staged window
 constexpr int kLdsGroup = 32;  // nuclides per staging round

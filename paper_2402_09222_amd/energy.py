@@ -72,7 +72,8 @@ def measure(fn, meter: EnergyMeter, min_seconds: float = 0.25,
     and joules per call = power x seconds per call.
 
     fn must enqueue device work on torch's current stream.  Returns
-    (seconds per call, joules per call, watts)."""
+    (seconds per call, joules per call, watts); measure.last holds the
+    window's length and the accumulator steps inside it."""
     import time
 
     import torch
@@ -97,6 +98,7 @@ def measure(fn, meter: EnergyMeter, min_seconds: float = 0.25,
 
     events = []
     marks = []  # readings just after the accumulator stepped
+    steps = 0   # accumulator steps seen inside the window
     last = reading()
     deadline = None
     limit = time.perf_counter() + 20.0 * max(min_seconds, 10 * one) + 5.0
@@ -108,6 +110,8 @@ def measure(fn, meter: EnergyMeter, min_seconds: float = 0.25,
         while len(events) >= depth and not events[0].query():
             r = reading()
             if r[0] != last[0]:
+                if marks:
+                    steps += 1
                 if len(marks) == 0 or (deadline and r[2] >= deadline):
                     marks.append(r)
                     if len(marks) == 1:
@@ -131,4 +135,5 @@ def measure(fn, meter: EnergyMeter, min_seconds: float = 0.25,
         if abs((ts1 - ts0) / unit - dt) < 0.2 * dt:
             dt = (ts1 - ts0) / unit
     watts = (e1 - e0) / dt
+    measure.last = {"window_s": dt, "steps": steps}
     return sec, watts * sec, watts
