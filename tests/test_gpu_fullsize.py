@@ -189,3 +189,40 @@ def test_requests_full(full, grid, prec):
         sel = full["pick"] < end
         assert sel.sum() > 100
         assert np.array_equal(got[full["pick"][sel]], full["ref32"][sel])
+
+
+def test_largest_batch(full):
+    """n = 2^31 - 1, the largest batch the interface takes (positions and the
+    permutation are int32): the full-size queries' first 2^20 repeated 2,048
+    times and cut one short.  Every repeat of the base chunk must give the
+    base chunk's bits (a property at any size), the base chunk must match the
+    oracle's samples, and both a sorted LDS-staged and an unsorted launch
+    shape must agree."""
+    if "out64" not in full:
+        pytest.skip("plain run failed")
+    c = 1 << 20
+    n = (1 << 31) - 1
+    say("largest batch", n)
+    E = full["E"][:c].repeat(2048)[:n]
+    m = full["m"][:c].repeat(2048)[:n]
+    base = full["out64"][:c].to(dtype=torch.float64)
+    pick = full["pick"][full["pick"] < c]
+    for kw in (dict(grid="unionized", sort="band_material", sort_threshold=0,
+                    block_size=128, lookups_per_thread=1, unroll=1,
+                    lds_stage=1),
+               dict(grid="hash", sort="none", block_size=256,
+                    lookups_per_thread=1, unroll=2)):
+        say("largest batch", kw)
+        p = xs.make_params(xs.XS_FP32, **kw)
+        out = xs.xs_lookup_batch(full["h"], E, m, params=p)
+        torch.cuda.synchronize()
+        first = out[:c]
+        got = first.cpu().numpy()
+        assert np.array_equal(got[pick], full["ref32"][:len(pick)]), kw
+        full_chunks = out[:2047 * c].view(2047, c, 5)
+        assert torch.equal(full_chunks, first.unsqueeze(0).expand(2047, c, 5)), kw
+        assert torch.equal(out[2047 * c:], first[:c - 1]), kw
+        rel = (first.double() - base).abs() / base
+        assert float(rel.max()) <= 2e-6
+        del out, first, full_chunks
+        torch.cuda.empty_cache()
