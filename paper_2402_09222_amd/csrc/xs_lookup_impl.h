@@ -739,7 +739,9 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
       if (first_rec >= 0 && k < s_width[i]) stage[s] = recs[first_rec + k];
     }
     __syncthreads();
-    for (int i = 0; i < cnt; ++i) {
+    // One nuclide of the group: its records (from LDS, or the lane's own
+    // search when the window was too wide), then the arithmetic.
+    auto step = [&](int i) {
       const int j = jg + i;
       const MatRec r = ld_const(t.mrec + j);
       const auto rho = Acc<PREC>::rho(t, r, j);
@@ -783,7 +785,19 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
       // one copy of the arithmetic for both paths
 #pragma unroll
       for (int l = 0; l < LPT; ++l) acc[l].add(lo[l], hi[l], e[l], rho);
+    };
+    // FP32: two nuclides per trip (in list order), so the Kahan accumulators
+    // alternate between two register sets instead of being copied back every
+    // nuclide.  FP64 keeps one per trip (measured: the second set of wide
+    // records costs more occupancy than the copies).
+    int i = 0;
+    if constexpr (PREC == XS_FP32) {
+      for (; i + 1 < cnt; i += 2) {
+        step(i);
+        step(i + 1);
+      }
     }
+    for (; i < cnt; ++i) step(i);
     __syncthreads();  // the stage and window tables are rewritten next group
   }
 #pragma unroll

@@ -205,7 +205,7 @@ def test_largest_batch(full):
     say("largest batch", n)
     E = full["E"][:c].repeat(2048)[:n]
     m = full["m"][:c].repeat(2048)[:n]
-    base = full["out64"][:c].to(dtype=torch.float64)
+    base = full["out64"][:c].to(device="cuda:0", dtype=torch.float64)
     pick = full["pick"][full["pick"] < c]
     for kw in (dict(grid="unionized", sort="band_material", sort_threshold=0,
                     block_size=128, lookups_per_thread=1, unroll=1,
