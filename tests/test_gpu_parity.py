@@ -228,16 +228,19 @@ def test_active_mask(cfg1, queue, sort):
     sentinel = -7.25
     for prec, ref in ((xs.XS_FP64, cfg1["ref"]), (xs.XS_FP32, cfg1["ref32"])):
         dt = torch.float64 if prec == xs.XS_FP64 else torch.float32
-        out = torch.full((n, 5), sentinel, dtype=dt, device="cuda:0")
-        p = xs.make_params(precision=prec, sort=sort, sort_threshold=0,
-                           queue=queue, lookups_per_thread=2)
-        xs.xs_lookup_active(cfg1["h"], cfg1["E"], cfg1["m"],
-                            dev(act, torch.uint8), out, params=p)
-        torch.cuda.synchronize()
-        o = out.cpu().numpy()
-        a = act.astype(bool)
-        assert np.all(o[~a] == sentinel)
-        assert np.array_equal(o[a], ref[a])
+        for shape in (dict(lookups_per_thread=2),
+                      dict(grid="unionized", lookups_per_thread=1, unroll=1,
+                           lds_stage=1, block_size=128)):
+            out = torch.full((n, 5), sentinel, dtype=dt, device="cuda:0")
+            p = xs.make_params(precision=prec, sort=sort, sort_threshold=0,
+                               queue=queue, **shape)
+            xs.xs_lookup_active(cfg1["h"], cfg1["E"], cfg1["m"],
+                                dev(act, torch.uint8), out, params=p)
+            torch.cuda.synchronize()
+            o = out.cpu().numpy()
+            a = act.astype(bool)
+            assert np.all(o[~a] == sentinel), shape
+            assert np.array_equal(o[a], ref[a]), shape
 
 
 def test_errors_from_device_calls(cfg1):
