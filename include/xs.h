@@ -128,9 +128,12 @@ typedef struct {
 /* Launch and method parameters of one lookup call.  Every field except
  * `precision` may be XS_AUTO (or 0 for block_size / lookups_per_thread), in
  * which case the value recorded by xs_tune for this precision and batch size
- * is used, else the library default (grid HASH if built else NUCLIDE, sort
- * BAND_MATERIAL at n >= 20,000, block 256, 1 lookup per thread, 2 nuclides
- * in flight).  The
+ * is used, else the library default: for n >= 262,144 (one query per lane
+ * of the chip) grid HASH if built else NUCLIDE, sort BAND_MATERIAL at
+ * n >= 20,000, block 256, 1 lookup per thread, 2 nuclides in flight; for
+ * smaller n one wave per lookup, grid UNIONIZED if built, unsorted, block
+ * 128.  An XS_AUTO wave_per_lookup becomes 0 wherever the fields set
+ * explicitly exclude it.  The
  * choice never changes the results: every combination returns the same
  * indices and, within one precision, bit-identical sums. */
 typedef struct {
@@ -152,6 +155,11 @@ typedef struct {
   int32_t queue;              /* xs_lookup_active only: XS_QUEUE_* */
   int32_t unroll;             /* nuclides in flight per lane: 1, 2 or 4
                                  (2 and 4 need lookups_per_thread <= 2) */
+  int32_t wave_per_lookup;    /* 1: the 64 lanes of a wave share one lookup,
+                                 each taking every 64th nuclide of its
+                                 material (small batches); needs
+                                 lookups_per_thread = unroll = 1, lds_stage
+                                 = 0 and block_size <= 256 */
 } xs_params;
 
 /* Sizes of a built handle. */

@@ -175,6 +175,10 @@ const xs_params* nearest_tuned(const xs_tables_s* h, int prec, int64_t n) {
   return best < 0 ? nullptr : &h->tuned[prec][best];
 }
 
+// Untuned batches smaller than one query per lane of the chip (256 compute
+// units x 1024 lanes) default to one wave per query.
+constexpr int64_t kWaveDefaultBelow = 256 * 1024;
+
 xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
                   xs_params* out) {
   xs_params p;
@@ -208,6 +212,16 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
     t.sort_threshold = 20000;
     t.queue = XS_QUEUE_COMPACT;
     t.unroll = 2;
+    t.wave_per_lookup = 0;
+    if (n < kWaveDefaultBelow) {
+      // Too few queries to give every lane of the chip one: a wave per
+      // query, unsorted, on the fastest grid that was built.
+      t.grid = h->d.U > 0 ? XS_GRID_UNIONIZED : t.grid;
+      t.sort = XS_SORT_NONE;
+      t.block_size = 128;
+      t.unroll = 1;
+      t.wave_per_lookup = 1;
+    }
   }
   if (p.grid == XS_AUTO) p.grid = t.grid;
   if (p.sort == XS_AUTO) p.sort = t.sort;
@@ -215,11 +229,19 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.lookups_per_thread == 0 || p.lookups_per_thread == XS_AUTO)
     p.lookups_per_thread = t.lookups_per_thread;
   if (p.lds_stage == XS_AUTO) p.lds_stage = t.lds_stage;
+  if (p.wave_per_lookup == XS_AUTO) {
+    // only where the fields set explicitly allow it
+    const bool fits = p.lookups_per_thread == 1 && p.lds_stage == 0 &&
+                      (p.unroll == 0 || p.unroll == XS_AUTO || p.unroll == 1) &&
+                      p.block_size <= 256;
+    p.wave_per_lookup = fits ? t.wave_per_lookup : 0;
+  }
   if (p.sort_threshold < 0) p.sort_threshold = t.sort_threshold;
   if (p.queue == XS_AUTO) p.queue = t.queue;
   if (p.unroll == 0 || p.unroll == XS_AUTO) {
     // the tuned depth when it applies and the block leaves room for it
-    const int u = (p.lookups_per_thread <= 2 && p.lds_stage != 1) ? t.unroll : 1;
+    const int u = (p.lookups_per_thread <= 2 && p.lds_stage != 1 &&
+                   p.wave_per_lookup != 1) ? t.unroll : 1;
     const int w = p.lookups_per_thread * u;
     const int max_block = w <= 1 ? 1024 : (w <= 4 ? 512 : 256);
     p.unroll = p.block_size <= max_block ? u : 1;
@@ -242,6 +264,13 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
     return fail(XS_EINVAL, "lds_stage = 1 runs one or two lookups per lane "
                 "with one nuclide in flight (lookups_per_thread <= 2, "
                 "unroll = 1)");
+  if (p.wave_per_lookup != 0 && p.wave_per_lookup != 1)
+    return fail(XS_EINVAL, "wave_per_lookup must be 0 or 1");
+  if (p.wave_per_lookup == 1 &&
+      (p.lookups_per_thread != 1 || p.unroll != 1 || p.lds_stage != 0 ||
+       p.block_size > 256))
+    return fail(XS_EINVAL, "wave_per_lookup = 1 needs lookups_per_thread = "
+                "unroll = 1, lds_stage = 0 and block_size <= 256");
   if (p.queue != XS_QUEUE_COMPACT && p.queue != XS_QUEUE_PREDICATED)
     return fail(XS_EINVAL, "unknown queue mode %d", p.queue);
   if (p.unroll != 1 && p.unroll != 2 && p.unroll != 4)
@@ -563,6 +592,7 @@ xs_status xs_params_default(xs_params* p, int32_t precision) {
   p->sort = XS_AUTO;
   p->block_size = 0;
   p->lookups_per_thread = 0;
+  p->wave_per_lookup = XS_AUTO;
   p->lds_stage = XS_AUTO;
   p->sort_threshold = -1;
   p->queue = XS_AUTO;

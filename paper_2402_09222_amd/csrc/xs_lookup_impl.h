@@ -282,15 +282,17 @@ struct Acc;
 
 template <>
 struct Acc<XS_FP64> {
+  using Term = double;
   double v[XS_CHANNELS];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int c = 0; c < XS_CHANNELS; ++c) v[c] = 0.0;
   }
-  // One nuclide's term: sigma = g*lo + f*hi (two products, one add), then
-  // sum += rho * sigma.
-  __device__ __forceinline__ void add(const Rec64& lo, const Rec64& hi,
-                                      double e, double rho) {
+  // One nuclide's terms: sigma = g*lo + f*hi (two products, one add), then
+  // rho * sigma.
+  __device__ __forceinline__ static void terms(const Rec64& lo, const Rec64& hi,
+                                               double e, double rho,
+                                               double (&t)[XS_CHANNELS]) {
     const double f = fraction(e, lo.e, hi.e);
     const double g = 1.0 - f;
 #pragma unroll
@@ -298,9 +300,19 @@ struct Acc<XS_FP64> {
       const double a = g * lo.x[c];
       const double b = f * hi.x[c];
       const double sigma = a + b;
-      const double term = rho * sigma;
-      v[c] = v[c] + term;
+      t[c] = rho * sigma;
     }
+  }
+  // sum += term, one channel.
+  __device__ __forceinline__ static void step(double& v, double term) {
+    v = v + term;
+  }
+  __device__ __forceinline__ void add(const Rec64& lo, const Rec64& hi,
+                                      double e, double rho) {
+    double t[XS_CHANNELS];
+    terms(lo, hi, e, rho, t);
+#pragma unroll
+    for (int c = 0; c < XS_CHANNELS; ++c) step(v[c], t[c]);
   }
   __device__ __forceinline__ static double rho(const DevTables& t,
                                                const MatRec&, int j) {
@@ -320,6 +332,7 @@ struct Acc<XS_FP64> {
 
 template <>
 struct Acc<XS_FP32> {
+  using Term = float;
   float s[XS_CHANNELS];
   float c[XS_CHANNELS];
   __device__ __forceinline__ void zero() {
@@ -330,10 +343,10 @@ struct Acc<XS_FP32> {
     }
   }
   // f and g = 1 - f are formed in FP64 and each rounded to FP32; channels
-  // interpolate in FP32; the sum over nuclides is compensated (Kahan):
-  // y = rho*sigma - c; t = s + y; c = (t - s) - y; s = t.
-  __device__ __forceinline__ void add(const Rec32& lo, const Rec32& hi,
-                                      double e, float rho) {
+  // interpolate in FP32; the term is rho * sigma in FP32.
+  __device__ __forceinline__ static void terms(const Rec32& lo, const Rec32& hi,
+                                               double e, float rho,
+                                               float (&t)[XS_CHANNELS]) {
     const double f = fraction(e, lo.e, hi.e);
     const float f32 = (float)f;
     const float g32 = (float)(1.0 - f);
@@ -342,12 +355,23 @@ struct Acc<XS_FP32> {
       const float a = g32 * lo.x[k];
       const float b = f32 * hi.x[k];
       const float sigma = a + b;
-      const float term = rho * sigma;
-      const float y = term - c[k];
-      const float tt = s[k] + y;
-      c[k] = (tt - s[k]) - y;
-      s[k] = tt;
+      t[k] = rho * sigma;
     }
+  }
+  // The sum over nuclides is compensated (Kahan), one channel:
+  // y = term - c; t = s + y; c = (t - s) - y; s = t.
+  __device__ __forceinline__ static void step(float& s, float& c, float term) {
+    const float y = term - c;
+    const float tt = s + y;
+    c = (tt - s) - y;
+    s = tt;
+  }
+  __device__ __forceinline__ void add(const Rec32& lo, const Rec32& hi,
+                                      double e, float rho) {
+    float t[XS_CHANNELS];
+    terms(lo, hi, e, rho, t);
+#pragma unroll
+    for (int k = 0; k < XS_CHANNELS; ++k) step(s[k], c[k], t[k]);
   }
   __device__ __forceinline__ static float rho(const DevTables&, const MatRec& r,
                                               int) {
@@ -362,6 +386,27 @@ struct Acc<XS_FP32> {
     float* p = (float*)out + o * XS_CHANNELS;
 #pragma unroll
     for (int k = 0; k < XS_CHANNELS; ++k) p[k] = __builtin_nanf("");
+  }
+};
+
+// One channel's running sum, for kernels that give each channel its own
+// lane: the same step as Acc<PREC>.
+template <int PREC>
+struct Chan;
+template <>
+struct Chan<XS_FP64> {
+  double v = 0.0;
+  __device__ __forceinline__ void add(double t) { Acc<XS_FP64>::step(v, t); }
+  __device__ __forceinline__ void store(void* out, int64_t i) const {
+    ((double*)out)[i] = v;
+  }
+};
+template <>
+struct Chan<XS_FP32> {
+  float s = 0.0f, c = 0.0f;
+  __device__ __forceinline__ void add(float t) { Acc<XS_FP32>::step(s, c, t); }
+  __device__ __forceinline__ void store(void* out, int64_t i) const {
+    ((float*)out)[i] = s;
   }
 };
 
@@ -804,6 +849,73 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
   for (int l = 0; l < LPT; ++l) acc[l].store(a.out, o[l]);
 }
 
+// ---- one wave per lookup ------------------------------------------------------------
+//
+// For small batches one lane per lookup leaves most of the chip idle, and
+// each lane walks its material's nuclides one after another, each behind a
+// chain of dependent loads (search, then records).  Here the 64 lanes of a
+// wave share one lookup: lane l takes nuclides l, l + 64, ... of the
+// material, finds its bracket, interpolates and forms its density-weighted
+// terms, which go through LDS to five lanes (one per channel) that add them
+// in list order.  Same terms, same order: the sums are bit-identical to
+// k_lookup's.  No block barrier is used, so a wave whose lookup is inactive
+// or invalid simply leaves.
+
+constexpr int kWaveBlock = 256;  // largest block: four waves
+
+template <int GRID, int PREC>
+__global__ __launch_bounds__(kWaveBlock) void k_lookup_wave(const DevTables t,
+                                                            const LookupArgs a) {
+  using R = typename RecOf<PREC>::T;
+  using T = typename Acc<PREC>::Term;
+  __shared__ T terms[kWaveBlock / 64][64][XS_CHANNELS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n = a.count_dev ? *a.count_dev : a.n;
+  const int64_t q = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
+  if (q >= n) return;
+  const int64_t o = a.perm ? (int64_t)a.perm[q] : q;
+  if ((uint64_t)o >= (uint64_t)a.n) return;
+  if (a.active && !a.active[o]) return;
+  const double e = a.E[o];
+  const int m = a.mat[o];
+  if (!valid_query(e, m, t.M)) {
+    if (lane == 0) Acc<PREC>::store_nan(a.out, o);
+    return;
+  }
+  Locator<GRID> loc;
+  loc.init(t, e, m);
+  Chan<PREC> sum;  // lanes 0..4: channel `lane`
+  const int j0 = t.moff[m], j1 = t.moff[m + 1];
+  for (int jc = j0; jc < j1; jc += 64) {
+    const int j = jc + lane;
+    if (j < j1) {
+      const MatRec r = t.mrec[j];
+      const int cand = loc.start(t, r, j, e);
+      Window<GRID, PREC> win;
+      win.load(t, r, cand);
+      R lo, hi;
+      win.finish(t, r, loc, cand, e, lo, hi);
+      T tm[XS_CHANNELS];
+      Acc<PREC>::terms(lo, hi, e, Acc<PREC>::rho(t, r, j), tm);
+#pragma unroll
+      for (int c = 0; c < XS_CHANNELS; ++c) terms[w][lane][c] = tm[c];
+    }
+    // the wave's LDS writes are visible to its own reads after this point
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < XS_CHANNELS) {
+      const int cnt = min(64, j1 - jc);
+      for (int i = 0; i < cnt; ++i) sum.add(terms[w][i][lane]);
+    }
+    // the terms are rewritten by the next chunk
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (lane < XS_CHANNELS) sum.store(a.out, o * XS_CHANNELS + lane);
+}
+
 // ---- launchers ------------------------------------------------------------------
 
 // (LPT, U) pairs instantiated: every LPT with one nuclide in flight, and 2 or
@@ -840,6 +952,22 @@ hipError_t launch_variant(const DevTables& t, int lpt, int unroll, dim3 grid,
 template <int GRID>
 hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
                               const LookupArgs& a, hipStream_t s) {
+  if (p.wave_per_lookup) {
+    if (p.lookups_per_thread != 1 || p.unroll != 1 || p.lds_stage ||
+        p.block_size > kWaveBlock)
+      return hipErrorInvalidValue;
+    const int64_t per_block = p.block_size / 64;
+    const int64_t nb = (a.n + per_block - 1) / per_block;
+    if (nb == 0) return hipSuccess;
+    if (nb > 0x7fffffff) return hipErrorInvalidValue;
+    if (p.precision == XS_FP64)
+      hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP64>), dim3((unsigned)nb),
+                         dim3(p.block_size), 0, s, t, a);
+    else
+      hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP32>), dim3((unsigned)nb),
+                         dim3(p.block_size), 0, s, t, a);
+    return hipGetLastError();
+  }
   if (p.lds_stage) {
     const int lpt = p.lookups_per_thread;
     if ((lpt != 1 && lpt != 2) || p.unroll != 1 ||

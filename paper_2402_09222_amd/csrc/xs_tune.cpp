@@ -34,7 +34,7 @@ namespace {
 
 // ---- the configuration space ---------------------------------------------
 
-constexpr int kNumFeatures = 13;
+constexpr int kNumFeatures = 14;
 
 struct Cand {
   xs_params p;
@@ -59,13 +59,16 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
     for (int s = 0; s < 5; ++s) {
       if (!(sorts >> s & 1u)) continue;
       for (int b : kBlocks) {
-        for (int vi = 0; vi < kNumVariants + 2; ++vi) {
-          // the last two variants are LDS staging with one or two lookups
-          // per lane (one nuclide in flight)
-          const bool lds = vi >= kNumVariants;
-          const int v[2] = {lds ? vi - kNumVariants + 1 : kVariants[vi][0],
-                            lds ? 1 : kVariants[vi][1]};
-          if (b > (lds ? 1024 / v[0] : max_block(v[0], v[1]))) continue;
+        for (int vi = 0; vi < kNumVariants + 3; ++vi) {
+          // then LDS staging with one or two lookups per lane (one nuclide
+          // in flight), then one wave per lookup
+          const bool lds = vi == kNumVariants || vi == kNumVariants + 1;
+          const bool wave = vi == kNumVariants + 2;
+          const int v[2] = {lds ? vi - kNumVariants + 1
+                                : (wave ? 1 : kVariants[vi][0]),
+                            lds || wave ? 1 : kVariants[vi][1]};
+          if (b > (wave ? 256 : (lds ? 1024 / v[0] : max_block(v[0], v[1]))))
+            continue;
           Cand c{};
           c.p.precision = precision;
           c.p.grid = g;
@@ -74,6 +77,7 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
           c.p.lookups_per_thread = v[0];
           c.p.unroll = v[1];
           c.p.lds_stage = lds ? 1 : 0;
+          c.p.wave_per_lookup = wave ? 1 : 0;
           c.p.sort_threshold =
               s == XS_SORT_NONE ? std::numeric_limits<int64_t>::max() : 0;
           c.p.queue = XS_QUEUE_COMPACT;
@@ -84,6 +88,7 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
           c.f[10] = (float)v[1];
           c.f[11] = (float)(v[0] * v[1]);
           c.f[12] = lds ? 1.f : 0.f;
+          c.f[13] = wave ? 1.f : 0.f;
           out.push_back(c);
         }
       }
@@ -93,8 +98,9 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
 }
 
 // Categorical dimensions of a candidate for the initial design: grid, sort,
-// block size, lookups per lane, nuclides in flight, LDS staging.
-constexpr int kDesignDims = 6;
+// block size, lookups per lane, nuclides in flight, LDS staging, wave per
+// lookup.
+constexpr int kDesignDims = 7;
 
 int design_level(const xs_params& p, int d) {
   switch (d) {
@@ -103,7 +109,8 @@ int design_level(const xs_params& p, int d) {
     case 2: return p.block_size;
     case 3: return p.lookups_per_thread;
     case 4: return p.unroll;
-    default: return p.lds_stage;
+    case 5: return p.lds_stage;
+    default: return p.wave_per_lookup;
   }
 }
 
@@ -260,7 +267,7 @@ class Forest {
 bool same_choice(const xs_params& a, const xs_params& b) {
   return a.grid == b.grid && a.sort == b.sort && a.block_size == b.block_size &&
          a.lookups_per_thread == b.lookups_per_thread && a.unroll == b.unroll &&
-         a.lds_stage == b.lds_stage;
+         a.lds_stage == b.lds_stage && a.wave_per_lookup == b.wave_per_lookup;
 }
 
 // ---- the search ---------------------------------------------------------------
@@ -553,7 +560,8 @@ xs_status xs_set_tuned(xs_tables_t h, int64_t n, const xs_params* p) {
   // Must be complete and valid on its own (no automatic fields).
   if (p->grid == XS_AUTO || p->sort == XS_AUTO || p->block_size <= 0 ||
       p->lookups_per_thread <= 0 || p->lds_stage == XS_AUTO ||
-      p->sort_threshold < 0 || p->queue == XS_AUTO || p->unroll <= 0)
+      p->sort_threshold < 0 || p->queue == XS_AUTO || p->unroll <= 0 ||
+      p->wave_per_lookup == XS_AUTO)
     return fail(XS_EINVAL, "tuned parameters must not contain automatic fields");
   xs_params checked;
   if (xs_status st = xs_resolve_params(h, n, p, &checked)) return st;

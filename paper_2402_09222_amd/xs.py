@@ -68,6 +68,7 @@ class xs_params(ctypes.Structure):
         ("sort_threshold", ctypes.c_int64),
         ("queue", ctypes.c_int32),
         ("unroll", ctypes.c_int32),
+        ("wave_per_lookup", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -296,13 +297,13 @@ def _stream_ptr(stream, device=None):
 
 def make_params(precision=XS_FP64, grid=XS_AUTO, sort=XS_AUTO, block_size=0,
                 lookups_per_thread=0, lds_stage=XS_AUTO, sort_threshold=-1,
-                queue=XS_AUTO, unroll=0) -> xs_params:
+                queue=XS_AUTO, unroll=0, wave_per_lookup=XS_AUTO) -> xs_params:
     if isinstance(grid, str):
         grid = GRIDS[grid]
     if isinstance(sort, str):
         sort = SORTS[sort]
     return xs_params(precision, grid, sort, block_size, lookups_per_thread,
-                     lds_stage, sort_threshold, queue, unroll)
+                     lds_stage, sort_threshold, queue, unroll, wave_per_lookup)
 
 
 class Tables:

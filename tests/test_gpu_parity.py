@@ -122,6 +122,10 @@ KNOBS = [
          lookups_per_thread=2, unroll=1, lds_stage=1),
     dict(sort="none", block_size=512, lookups_per_thread=2, unroll=1,
          lds_stage=1),
+    dict(sort="none", block_size=256, lookups_per_thread=1, unroll=1,
+         lds_stage=0, wave_per_lookup=1),
+    dict(sort="band_material", sort_threshold=0, block_size=64,
+         lookups_per_thread=1, unroll=1, lds_stage=0, wave_per_lookup=1),
 ]
 
 
@@ -140,9 +144,20 @@ def test_default_params(cfg1):
     out = xs.xs_lookup_batch(cfg1["h"], cfg1["E"], cfg1["m"])
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), cfg1["ref"])
-    p = xs.xs_resolve_params(cfg1["h"], 100000)
+    p = xs.xs_resolve_params(cfg1["h"], 300000)
     assert p.grid == xs.XS_GRID_HASH and p.block_size == 256
     assert p.sort == xs.XS_SORT_BAND_MATERIAL and p.unroll == 2
+    assert p.wave_per_lookup == 0
+    # fewer queries than lanes on the chip: one wave per query, unsorted
+    p = xs.xs_resolve_params(cfg1["h"], 100000)
+    assert p.grid == xs.XS_GRID_UNIONIZED and p.block_size == 128
+    assert p.sort == xs.XS_SORT_NONE and p.wave_per_lookup == 1
+    assert p.unroll == 1 and p.lookups_per_thread == 1
+    # explicit fields that exclude it keep one lane per query
+    for kw in (dict(lookups_per_thread=2), dict(block_size=512),
+               dict(unroll=2), dict(lds_stage=1)):
+        p = xs.xs_resolve_params(cfg1["h"], 100000, xs.make_params(**kw))
+        assert p.wave_per_lookup == 0, kw
 
 
 def test_edge_queries(cfg1):
@@ -255,7 +270,11 @@ def test_errors_from_device_calls(cfg1):
                 dict(sort=5), dict(grid=3), dict(lds_stage=2),
                 dict(lds_stage=1, lookups_per_thread=3),
                 dict(lds_stage=1, lookups_per_thread=2, block_size=1024),
-                dict(lds_stage=1, unroll=2)):
+                dict(lds_stage=1, unroll=2), dict(wave_per_lookup=2),
+                dict(wave_per_lookup=1, block_size=512, unroll=1),
+                dict(wave_per_lookup=1, lookups_per_thread=2, unroll=1),
+                dict(wave_per_lookup=1, unroll=2),
+                dict(wave_per_lookup=1, lds_stage=1, unroll=1)):
         with pytest.raises(xs.XsError) as e:
             xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"],
                                params=xs.make_params(**bad))

@@ -33,7 +33,8 @@ def cost(p):
     w = p.lookups_per_thread * p.unroll
     ilp = 1.0 + 0.08 * abs(w - 2) + (0.3 if p.grid == 0 and p.unroll > 1 else 0)
     lds = 1.1 if p.lds_stage else 1.0
-    return grid * sort * blk * ilp * lds
+    wave = 1.3 if p.wave_per_lookup else 1.0
+    return grid * sort * blk * ilp * lds * wave
 
 
 class Recorder:
@@ -46,7 +47,7 @@ class Recorder:
         self.calls.append(dict(grid=p.grid, sort=p.sort, bs=p.block_size,
                                lpt=p.lookups_per_thread, u=p.unroll,
                                thr=p.sort_threshold, lds=p.lds_stage,
-                               prec=p.precision))
+                               wave=p.wave_per_lookup, prec=p.precision))
         self.cutoffs.append(cutoff)
         return self.fn(p)
 
@@ -60,6 +61,9 @@ def all_valid(calls):
         assert c["lds"] in (0, 1)
         assert c["lds"] == 0 or (c["lpt"] <= 2 and c["u"] == 1 and
                                  c["bs"] <= 1024 // c["lpt"])
+        assert c["wave"] in (0, 1)
+        assert c["wave"] == 0 or (c["lpt"] == 1 and c["u"] == 1 and
+                                  c["lds"] == 0 and c["bs"] <= 256)
         # conditional parameter: the threshold only means something when a
         # sort is selected; it is never varied within a policy
         assert c["thr"] == (INT64_MAX if c["sort"] == 0 else 0)
@@ -72,8 +76,8 @@ def test_exhaustive_finds_optimum():
     r = xs.xs_tune_search(7, cfg, rec)
     assert r.evaluated == r.space_size == len(rec.calls)
     all_valid(rec.calls)
-    keys = {(c["grid"], c["sort"], c["bs"], c["lpt"], c["u"], c["lds"])
-            for c in rec.calls}
+    keys = {(c["grid"], c["sort"], c["bs"], c["lpt"], c["u"], c["lds"],
+             c["wave"]) for c in rec.calls}
     assert len(keys) == len(rec.calls)  # no configuration twice
     best = min(cost_of(c) for c in rec.calls)
     assert r.best_ms == pytest.approx(best)
@@ -85,7 +89,8 @@ def test_exhaustive_finds_optimum():
 def cost_of(c):
     p = xs.make_params(c["prec"], grid=c["grid"], sort=c["sort"],
                        block_size=c["bs"], lookups_per_thread=c["lpt"],
-                       unroll=c["u"], lds_stage=c["lds"])
+                       unroll=c["u"], lds_stage=c["lds"],
+                       wave_per_lookup=c["wave"])
     return cost(p)
 
 
@@ -95,6 +100,7 @@ def test_space_size_matches_enumeration():
         n += sum(1 for b in BLOCKS if b <= max_block(lpt, u))
     for lpt in (1, 2):  # LDS staging
         n += sum(1 for b in BLOCKS if b <= 1024 // lpt)
+    n += sum(1 for b in BLOCKS if b <= 256)  # one wave per lookup
     for grids, mult in ((7, 3), (1, 1), (5, 2)):
         cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0)
         r = xs.xs_tune_search(grids, cfg, Recorder())
