@@ -256,6 +256,7 @@ def sweep_in_flight(args, torch, synth, xs):
             p.precision, p.grid, p.sort = best.precision, best.grid, sp
             p.block_size, p.lookups_per_thread = best.block_size, best.lookups_per_thread
             p.unroll, p.lds_stage, p.queue = best.unroll, best.lds_stage, best.queue
+            p.wave_per_lookup = best.wave_per_lookup
             p.sort_threshold = 0 if sp else xs.INT64_MAX
             row[f"fp32_sort_{name}_lookups_per_s"] = rate(p)
         print(json.dumps(row), flush=True)

@@ -493,6 +493,39 @@ xs_status xs_profile_begin(xs_tables_t tables);
  * recording. */
 xs_status xs_profile_end(xs_tables_t tables, xs_profile_t* out);
 
+/* ---- debug mode ---------------------------------------------------------- */
+
+/* Counters of debug mode (all 0 and on = 0 while it is off). */
+typedef struct {
+  int32_t on;
+  int32_t reserved;
+  int64_t calls;              /* lookup calls checked since it was switched on */
+  int64_t invalid_queries;    /* invalid queries those calls met */
+  int64_t hash_bin_scans;     /* hash-grid searches whose fast two-interval
+                                 window missed, so the bin was scanned */
+  int64_t hash_full_searches; /* of those, searches whose verify failed (the
+                                 rounding of log put E in a neighbouring bin)
+                                 and that bisected the whole grid */
+} xs_debug_info;
+
+/* Switches debug mode of the handle on (1) or off (0); off at creation;
+ * switching on clears the counters.  Call it while no work on the handle is
+ * in flight: it synchronises the device.  While on:
+ *  - xs_lookup_batch, xs_lookup_active and xs_lookup_indices (and what runs
+ *    through them: xs_lookup_requests with a sort, xs_event_run) count the
+ *    call's invalid queries (E not finite or <= 0, material outside
+ *    [0, n_materials); inactive slots excluded), wait for the stream, and
+ *    return XS_EINVAL naming their number and the first position when there
+ *    are any; the results are written as usual (NaN rows, -1 indices).
+ *    Debug calls cannot be captured into a graph (they synchronise);
+ *  - every hash-grid search counts how often it left the fast window and how
+ *    often it fell back to a full bisection (section 5.1's hash grid trades
+ *    bins for search length; these counters show that trade directly). */
+xs_status xs_set_debug(xs_tables_t tables, int32_t on);
+
+/* Reads the counters (synchronises the device). */
+xs_status xs_debug_counters(xs_tables_t tables, xs_debug_info* out);
+
 /* ---- errors ------------------------------------------------------------ */
 
 const char* xs_status_string(xs_status status);

@@ -347,6 +347,26 @@ hipEvent_t take_event(xs_tables_s* h) {
   return e;
 }
 
+// Debug mode: counts the call's invalid queries, waits for the stream and
+// fails with their number and the first position.
+xs_status debug_check(xs_tables_s* h, int64_t n, const double* E,
+                      const int32_t* mat, const uint8_t* active,
+                      hipStream_t s) {
+  XS_HIP(launch_debug_count(n, E, mat, active, h->d.M, h->dbg_dev, s));
+  unsigned long long c[kDbgWords];
+  XS_HIP(hipMemcpyAsync(c, h->dbg_dev, sizeof(c), hipMemcpyDeviceToHost, s));
+  XS_HIP(hipStreamSynchronize(s));
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    ++h->dbg_calls;
+  }
+  if (c[kDbgCallInvalid])
+    return fail(XS_EINVAL, "%llu of %lld queries are invalid (first at %llu): "
+                "energies must be finite and > 0, materials in [0, %d)",
+                c[kDbgCallInvalid], (long long)n, c[kDbgCallFirst], h->d.M);
+  return XS_OK;
+}
+
 xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
                         const int32_t* mat, const uint8_t* active, bool masked,
                         void* out, const xs_params* params, void* ws,
@@ -415,6 +435,8 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
     std::lock_guard<std::mutex> lk(h->mu);
     h->prof.push_back(pc);
   }
+  if (h->d.dbg)
+    return debug_check(h, n, E, mat, masked ? active : nullptr, s);
   return XS_OK;
 }
 
@@ -675,6 +697,53 @@ xs_status xs_lookup_indices(xs_tables_t h, int64_t n, const double* d_E,
   }
   if (e != hipSuccess)
     return fail(XS_EHIP, "index kernel launch failed: %s", hipGetErrorString(e));
+  if (h->d.dbg) return debug_check(h, n, d_E, d_mat, nullptr, s);
+  return XS_OK;
+}
+
+xs_status xs_set_debug(xs_tables_t h, int32_t on) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (on != 0 && on != 1) return fail(XS_EINVAL, "on must be 0 or 1");
+  int dev = -1;
+  XS_HIP(hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(XS_EINVAL, "current device %d is not the tables' device %d",
+                dev, h->device);
+  if (on && !h->dbg_dev) {
+    void* p = nullptr;
+    if (xs_status st = alloc_dev(h, kDbgWords * sizeof(unsigned long long), &p))
+      return st;
+    h->dbg_dev = (unsigned long long*)p;
+  }
+  if (on) {
+    XS_HIP(hipDeviceSynchronize());
+    XS_HIP(hipMemset(h->dbg_dev, 0, kDbgWords * sizeof(unsigned long long)));
+    XS_HIP(hipDeviceSynchronize());
+  }
+  std::lock_guard<std::mutex> lk(h->mu);
+  h->d.dbg = on ? h->dbg_dev : nullptr;
+  h->dbg_calls = 0;
+  return XS_OK;
+}
+
+xs_status xs_debug_counters(xs_tables_t h, xs_debug_info* out) {
+  clear_error();
+  if (xs_status st = check_handle(h)) return st;
+  if (!out) return fail(XS_EINVAL, "out is NULL");
+  xs_debug_info r{};
+  if (h->d.dbg) {
+    unsigned long long c[kDbgWords];
+    XS_HIP(hipDeviceSynchronize());
+    XS_HIP(hipMemcpy(c, h->dbg_dev, sizeof(c), hipMemcpyDeviceToHost));
+    r.invalid_queries = (int64_t)c[kDbgInvalid];
+    r.hash_bin_scans = (int64_t)c[kDbgHashScans];
+    r.hash_full_searches = (int64_t)c[kDbgHashFull];
+    std::lock_guard<std::mutex> lk(h->mu);
+    r.calls = h->dbg_calls;
+    r.on = 1;
+  }
+  *out = r;
   return XS_OK;
 }
 

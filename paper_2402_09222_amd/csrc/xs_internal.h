@@ -61,6 +61,22 @@ struct DevTables {
   const int32_t* uidx;       // [U][K], or per material m a block [U][L_m]
                              // at U * moff[m] (union_by_material)
   int32_t union_by_material;
+  // debug counters, null unless the handle is in debug mode:
+  // [kDbgHashScans] hash searches that left the fast two-interval window,
+  // [kDbgHashFull] of those, searches that fell back to full bisection
+  unsigned long long* dbg;
+};
+
+// Device debug counters (8 words): the two above, then the invalid queries
+// of all debug calls, of the current call, and the lowest invalid position
+// of the current call.
+enum : int {
+  kDbgHashScans = 0,
+  kDbgHashFull = 1,
+  kDbgInvalid = 2,
+  kDbgCallInvalid = 3,
+  kDbgCallFirst = 4,
+  kDbgWords = 8
 };
 
 // ---- sort key ------------------------------------------------------------
@@ -111,6 +127,9 @@ struct xs_tables_s {
   void* req_stage = nullptr;
   size_t req_stage_bytes = 0;
   hipEvent_t req_event = nullptr;
+  // debug mode (xs_set_debug): device counters and calls checked since on
+  unsigned long long* dbg_dev = nullptr;
+  int64_t dbg_calls = 0;
 };
 
 namespace xs {
@@ -126,6 +145,13 @@ void clear_error();
       return ::xs::fail(e_ == hipErrorOutOfMemory ? XS_ENOMEM : XS_EHIP,  \
                         "%s failed: %s", #call, hipGetErrorString(e_));   \
   } while (0)
+
+// Debug mode (xs_debug.hip): resets the current call's words of `counters`
+// and counts the invalid queries among the first n (active ones only when
+// `active` is not null).
+hipError_t launch_debug_count(int64_t n, const double* E, const int32_t* mat,
+                              const uint8_t* active, int M,
+                              unsigned long long* counters, hipStream_t s);
 
 // Table builders (xs_build.hip).
 hipError_t launch_hash_build(const DevTables& t, const int32_t* goff_dev,

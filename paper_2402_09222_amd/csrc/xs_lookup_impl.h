@@ -110,6 +110,10 @@ __device__ __forceinline__ int hash_slow(const DevTables& t, const MatRec& r,
   int p = lo;
   while (p < hi && g[p + 1] <= e) ++p;
   const bool ok = (p == 0 || g[p] <= e) && (p == r.n - 2 || e < g[p + 1]);
+  if (t.dbg) {
+    atomicAdd(t.dbg + kDbgHashScans, 1ull);
+    if (!ok) atomicAdd(t.dbg + kDbgHashFull, 1ull);
+  }
   return ok ? p : min(bisect_le(g, r.n, e), r.n - 2);
 }
 
@@ -644,7 +648,7 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 // lowest and highest energies.  The material's nuclides are taken in groups
 // of kLdsGroup: lane i of the block finds the window of nuclide i of the
 // group (from the lower edge's bracket to the upper edge's bracket + 1), the
-// block copies every window of at most kLdsW records into LDS with one
+// block copies every window of at most lds_window records into LDS with one
 // cooperative read, and each lane then walks the group's nuclides in list
 // order, bisecting its window in LDS and interpolating from it.  A nuclide
 // whose window is wider takes the per-lane search for that nuclide; a block
@@ -655,13 +659,21 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 // lookups; the block's energy range covers all of them and their in-LDS
 // searches run in lock step.
 
-constexpr int kLdsW = 8;       // records per staged window
+// Records per staged window: 8 in FP32 (32-byte records), 6 in FP64, whose
+// 48-byte records would otherwise limit the blocks per compute unit by LDS
+// (measured on 10M banded lookups: the best FP64 staged launch 1.82 ms
+// against 2.0; FP32 unchanged).
+template <int PREC>
+constexpr int lds_window() {
+  return PREC == XS_FP64 ? 6 : 8;
+}
 constexpr int kLdsGroup = 32;  // nuclides per staging round
 
 template <int GRID, int PREC, int LPT>
 __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
                                                            const LookupArgs a) {
   using R = typename RecOf<PREC>::T;
+  constexpr int kLdsW = lds_window<PREC>();
   __shared__ R stage[kLdsGroup * kLdsW];
   __shared__ int s_first[kLdsGroup];  // first staged record, or -1: per lane
   __shared__ int s_width[kLdsGroup];  // records in the window

@@ -99,6 +99,20 @@ class xs_table_info_t(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class xs_debug_info(ctypes.Structure):
+    _fields_ = [
+        ("on", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("calls", ctypes.c_int64),
+        ("invalid_queries", ctypes.c_int64),
+        ("hash_bin_scans", ctypes.c_int64),
+        ("hash_full_searches", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class xs_profile_t(ctypes.Structure):
     _fields_ = [
         ("ms_sort", ctypes.c_double),
@@ -241,6 +255,8 @@ def load_library(path: str = LIB_PATH):
         "xs_lookup_indices": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
         "xs_profile_begin": ([vp], i32),
         "xs_profile_end": ([vp, P(xs_profile_t)], i32),
+        "xs_set_debug": ([vp, i32], i32),
+        "xs_debug_counters": ([vp, P(xs_debug_info)], i32),
         "xs_tune_config_default": ([P(xs_tune_config)], i32),
         "xs_tune_search": ([ctypes.c_uint32, P(xs_tune_config), EVAL_FN, vp,
                             P(xs_tune_result)], i32),
@@ -505,6 +521,18 @@ def xs_profile_end(tables: Tables) -> dict:
     _check(load_library().xs_profile_end(tables.handle, ctypes.byref(p)),
            "xs_profile_end")
     return p.as_dict()
+
+
+def xs_set_debug(tables: Tables, on: bool) -> None:
+    _check(load_library().xs_set_debug(tables.handle, 1 if on else 0),
+           "xs_set_debug")
+
+
+def xs_debug_counters(tables: Tables) -> dict:
+    d = xs_debug_info()
+    _check(load_library().xs_debug_counters(tables.handle, ctypes.byref(d)),
+           "xs_debug_counters")
+    return d.as_dict()
 
 
 def xs_tune_config_default(**over) -> xs_tune_config:

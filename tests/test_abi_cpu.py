@@ -36,7 +36,7 @@ def test_exports_every_declared_function(lib):
 STRUCTS = ["xs_table_desc", "xs_params", "xs_table_info_t", "xs_profile_t",
            "xs_tune_config", "xs_tune_result", "xs_request",
            "xs_request_stats", "xs_event_config", "xs_event_buffers",
-           "xs_event_result"]
+           "xs_event_result", "xs_debug_info"]
 
 
 def test_struct_layouts_match_header(tmp_path):
