@@ -111,11 +111,12 @@ def lookup_sources_hash() -> str:
 
 def kernel_name(p) -> str:
     """The lookup kernel a resolved parameter set launches, as rocprofv3
-    names it (template arguments: grid, precision, LPT[, U])."""
+    names it (template arguments: grid, precision, LPT[, U or stage shape])."""
     if getattr(p, "wave_per_lookup", 0) == 1:
         return f"k_lookup_wave<{p.grid}, {p.precision}>"
     if p.lds_stage:
-        return f"k_lookup_lds<{p.grid}, {p.precision}, {p.lookups_per_thread}>"
+        return (f"k_lookup_lds<{p.grid}, {p.precision}, {p.lookups_per_thread}, "
+                f"{p.lds_stage}>")
     return (f"k_lookup<{p.grid}, {p.precision}, {p.lookups_per_thread}, "
             f"{p.unroll}>")
 

@@ -143,13 +143,16 @@ typedef struct {
   int32_t block_size;         /* 64..1024, multiple of 64; with
                                  w = lookups_per_thread * unroll, at most 512
                                  when w > 1 and 256 when w > 4; with
-                                 lds_stage = 1 at most 1024 /
+                                 lds_stage > 0 at most 1024 /
                                  lookups_per_thread */
   int32_t lookups_per_thread; /* 1..8 */
-  int32_t lds_stage;          /* 1: blocks whose lookups share a material
-                                 stage each nuclide's bracket window in LDS
-                                 (needs lookups_per_thread <= 2 and
-                                 unroll = 1) */
+  int32_t lds_stage;          /* 0: off; 1, 2, 3: blocks whose lookups share
+                                 a material stage each nuclide's bracket
+                                 window in LDS, 32 nuclides with windows of
+                                 up to 8 records (6 in FP64) per round, 16
+                                 with 16 (12), or 8 with 32 (24): wider
+                                 windows suit sparser batches.  Needs
+                                 lookups_per_thread <= 2 and unroll = 1 */
   int64_t sort_threshold;     /* sort only when n >= sort_threshold
                                  (0 = always, INT64_MAX = never) */
   int32_t queue;              /* xs_lookup_active only: XS_QUEUE_* */

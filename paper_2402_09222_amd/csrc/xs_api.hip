@@ -240,7 +240,7 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.queue == XS_AUTO) p.queue = t.queue;
   if (p.unroll == 0 || p.unroll == XS_AUTO) {
     // the tuned depth when it applies and the block leaves room for it
-    const int u = (p.lookups_per_thread <= 2 && p.lds_stage != 1 &&
+    const int u = (p.lookups_per_thread <= 2 && p.lds_stage == 0 &&
                    p.wave_per_lookup != 1) ? t.unroll : 1;
     const int w = p.lookups_per_thread * u;
     const int max_block = w <= 1 ? 1024 : (w <= 4 ? 512 : 256);
@@ -258,10 +258,10 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.lookups_per_thread < 1 || p.lookups_per_thread > 8)
     return fail(XS_EINVAL, "lookups_per_thread %d not in 1..8",
                 p.lookups_per_thread);
-  if (p.lds_stage != 0 && p.lds_stage != 1)
-    return fail(XS_EINVAL, "lds_stage must be 0 or 1");
-  if (p.lds_stage == 1 && (p.lookups_per_thread > 2 || p.unroll != 1))
-    return fail(XS_EINVAL, "lds_stage = 1 runs one or two lookups per lane "
+  if (p.lds_stage < 0 || p.lds_stage > 3)
+    return fail(XS_EINVAL, "lds_stage must be 0 (off) or a stage shape 1..3");
+  if (p.lds_stage > 0 && (p.lookups_per_thread > 2 || p.unroll != 1))
+    return fail(XS_EINVAL, "lds_stage > 0 runs one or two lookups per lane "
                 "with one nuclide in flight (lookups_per_thread <= 2, "
                 "unroll = 1)");
   if (p.wave_per_lookup != 0 && p.wave_per_lookup != 1)
@@ -280,7 +280,7 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
                 p.unroll);
   {
     const int w = p.lookups_per_thread * p.unroll;
-    const int max_block = p.lds_stage == 1
+    const int max_block = p.lds_stage > 0
                               ? 1024 / p.lookups_per_thread
                               : (w <= 1 ? 1024 : (w <= 4 ? 512 : 256));
     if (p.block_size > max_block)

@@ -646,7 +646,7 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 // For a block whose lookups all share one material (the usual case after a
 // sort), each nuclide's bracket lies between the brackets of the block's
 // lowest and highest energies.  The material's nuclides are taken in groups
-// of kLdsGroup: lane i of the block finds the window of nuclide i of the
+// of lds_group: lane i of the block finds the window of nuclide i of the
 // group (from the lower edge's bracket to the upper edge's bracket + 1), the
 // block copies every window of at most lds_window records into LDS with one
 // cooperative read, and each lane then walks the group's nuclides in list
@@ -659,21 +659,28 @@ __global__ __launch_bounds__(256) void k_indices(const DevTables t, int64_t n,
 // lookups; the block's energy range covers all of them and their in-LDS
 // searches run in lock step.
 
-// Records per staged window: 8 in FP32 (32-byte records), 6 in FP64, whose
-// 48-byte records would otherwise limit the blocks per compute unit by LDS
-// (measured on 10M banded lookups: the best FP64 staged launch 1.82 ms
-// against 2.0; FP32 unchanged).
-template <int PREC>
-constexpr int lds_window() {
-  return PREC == XS_FP64 ? 6 : 8;
+// Stage shapes (lds_stage = 1, 2, 3): 32 nuclides per round with windows of
+// at most 8 records, 16 with 16, or 8 with 32 — the same LDS either way.
+// Dense batches (about 10M lookups) keep the windows narrow and favour many
+// nuclides per round; sparser ones (1e6 to 2e6) need wider windows, or most
+// nuclides fall back to the per-lane search (measured: 0.39 ms against 0.81
+// for the lookup of 1e6 banded lookups).  FP64 windows hold three quarters
+// as many of its 48-byte records, which would otherwise limit the blocks per
+// compute unit by LDS (10M banded lookups: 1.82 ms against 2.0).
+template <int SHAPE>
+constexpr int lds_group() {
+  return SHAPE == 1 ? 32 : (SHAPE == 2 ? 16 : 8);
 }
-constexpr int kLdsGroup = 32;  // nuclides per staging round
-
-template <int GRID, int PREC, int LPT>
+template <int PREC, int SHAPE>
+constexpr int lds_window() {
+  return (PREC == XS_FP64 ? 3 : 4) * (256 / lds_group<SHAPE>()) / 4;
+}
+template <int GRID, int PREC, int LPT, int SHAPE>
 __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
                                                            const LookupArgs a) {
   using R = typename RecOf<PREC>::T;
-  constexpr int kLdsW = lds_window<PREC>();
+  constexpr int kLdsGroup = lds_group<SHAPE>();
+  constexpr int kLdsW = lds_window<PREC, SHAPE>();
   __shared__ R stage[kLdsGroup * kLdsW];
   __shared__ int s_first[kLdsGroup];  // first staged record, or -1: per lane
   __shared__ int s_width[kLdsGroup];  // records in the window
@@ -985,17 +992,25 @@ hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
     if ((lpt != 1 && lpt != 2) || p.unroll != 1 ||
         p.block_size > 1024 / lpt)
       return hipErrorInvalidValue;
+    if (p.lds_stage < 1 || p.lds_stage > 3) return hipErrorInvalidValue;
     const int64_t per_block = (int64_t)p.block_size * lpt;
     const int64_t nb = (a.n + per_block - 1) / per_block;
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb), block((unsigned)p.block_size);
-#define XS_LDS(P, L) hipLaunchKernelGGL((k_lookup_lds<GRID, P, L>), grid, block, 0, s, t, a)
+#define XS_LDS(P, L, S) hipLaunchKernelGGL((k_lookup_lds<GRID, P, L, S>), grid, block, 0, s, t, a)
+#define XS_LDS_SHAPES(P, L)        \
+  switch (p.lds_stage) {           \
+    case 1: XS_LDS(P, L, 1); break; \
+    case 2: XS_LDS(P, L, 2); break; \
+    default: XS_LDS(P, L, 3); break; \
+  }
     if (p.precision == XS_FP64) {
-      if (lpt == 1) XS_LDS(XS_FP64, 1); else XS_LDS(XS_FP64, 2);
+      if (lpt == 1) { XS_LDS_SHAPES(XS_FP64, 1) } else { XS_LDS_SHAPES(XS_FP64, 2) }
     } else {
-      if (lpt == 1) XS_LDS(XS_FP32, 1); else XS_LDS(XS_FP32, 2);
+      if (lpt == 1) { XS_LDS_SHAPES(XS_FP32, 1) } else { XS_LDS_SHAPES(XS_FP32, 2) }
     }
+#undef XS_LDS_SHAPES
 #undef XS_LDS
     return hipGetLastError();
   }

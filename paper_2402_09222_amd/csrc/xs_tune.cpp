@@ -59,12 +59,14 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
     for (int s = 0; s < 5; ++s) {
       if (!(sorts >> s & 1u)) continue;
       for (int b : kBlocks) {
-        for (int vi = 0; vi < kNumVariants + 3; ++vi) {
-          // then LDS staging with one or two lookups per lane (one nuclide
-          // in flight), then one wave per lookup
-          const bool lds = vi == kNumVariants || vi == kNumVariants + 1;
-          const bool wave = vi == kNumVariants + 2;
-          const int v[2] = {lds ? vi - kNumVariants + 1
+        for (int vi = 0; vi < kNumVariants + 7; ++vi) {
+          // then LDS staging in each of the three stage shapes with one or
+          // two lookups per lane (one nuclide in flight), then one wave per
+          // lookup
+          const bool lds = vi >= kNumVariants && vi < kNumVariants + 6;
+          const bool wave = vi == kNumVariants + 6;
+          const int shape = lds ? (vi - kNumVariants) / 2 + 1 : 0;
+          const int v[2] = {lds ? (vi - kNumVariants) % 2 + 1
                                 : (wave ? 1 : kVariants[vi][0]),
                             lds || wave ? 1 : kVariants[vi][1]};
           if (b > (wave ? 256 : (lds ? 1024 / v[0] : max_block(v[0], v[1]))))
@@ -76,7 +78,7 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
           c.p.block_size = b;
           c.p.lookups_per_thread = v[0];
           c.p.unroll = v[1];
-          c.p.lds_stage = lds ? 1 : 0;
+          c.p.lds_stage = shape;
           c.p.wave_per_lookup = wave ? 1 : 0;
           c.p.sort_threshold =
               s == XS_SORT_NONE ? std::numeric_limits<int64_t>::max() : 0;
@@ -87,7 +89,7 @@ std::vector<Cand> enumerate_space(int precision, uint32_t grids,
           c.f[9] = (float)v[0];
           c.f[10] = (float)v[1];
           c.f[11] = (float)(v[0] * v[1]);
-          c.f[12] = lds ? 1.f : 0.f;
+          c.f[12] = (float)shape;
           c.f[13] = wave ? 1.f : 0.f;
           out.push_back(c);
         }

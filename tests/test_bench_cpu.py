@@ -39,7 +39,10 @@ def test_kernel_names_and_traffic_keys():
     from paper_2402_09222_amd import xs
     p = xs.make_params(xs.XS_FP32, grid=2, lookups_per_thread=1, unroll=1,
                        lds_stage=1)
-    assert bench.kernel_name(p) == "k_lookup_lds<2, 1, 1>"
+    assert bench.kernel_name(p) == "k_lookup_lds<2, 1, 1, 1>"
+    p = xs.make_params(xs.XS_FP32, grid=2, lookups_per_thread=2, unroll=1,
+                       lds_stage=3)
+    assert bench.kernel_name(p) == "k_lookup_lds<2, 1, 2, 3>"
     p = xs.make_params(xs.XS_FP64, grid=0, lookups_per_thread=1, unroll=2,
                        lds_stage=0)
     assert bench.kernel_name(p) == "k_lookup<0, 0, 1, 2>"

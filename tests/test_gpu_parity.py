@@ -122,6 +122,16 @@ KNOBS = [
          lookups_per_thread=2, unroll=1, lds_stage=1),
     dict(sort="none", block_size=512, lookups_per_thread=2, unroll=1,
          lds_stage=1),
+    dict(sort="band_material", sort_threshold=0, block_size=64,
+         lookups_per_thread=1, unroll=1, lds_stage=2),
+    dict(sort="material_energy", sort_threshold=0, block_size=256,
+         lookups_per_thread=2, unroll=1, lds_stage=2),
+    dict(sort="band_material", sort_threshold=0, block_size=128,
+         lookups_per_thread=1, unroll=1, lds_stage=3),
+    dict(sort="none", block_size=1024, lookups_per_thread=1, unroll=1,
+         lds_stage=3),
+    dict(sort="band_material", sort_threshold=0, block_size=512,
+         lookups_per_thread=2, unroll=1, lds_stage=3),
     dict(sort="none", block_size=256, lookups_per_thread=1, unroll=1,
          lds_stage=0, wave_per_lookup=1),
     dict(sort="band_material", sort_threshold=0, block_size=64,
@@ -267,7 +277,8 @@ def test_errors_from_device_calls(cfg1):
     for bad in (dict(block_size=1024, lookups_per_thread=5),
                 dict(block_size=1024, lookups_per_thread=2, unroll=2),
                 dict(lookups_per_thread=3, unroll=2), dict(unroll=3),
-                dict(sort=5), dict(grid=3), dict(lds_stage=2),
+                dict(sort=5), dict(grid=3), dict(lds_stage=4),
+                dict(lds_stage=-2),
                 dict(lds_stage=1, lookups_per_thread=3),
                 dict(lds_stage=1, lookups_per_thread=2, block_size=1024),
                 dict(lds_stage=1, unroll=2), dict(wave_per_lookup=2),
@@ -346,7 +357,8 @@ def test_lds_staging_groups(union_by_material):
     """LDS staging on materials longer than one staging group (70 and 33
     nuclides) with windows that fit (small blocks) and windows that do not
     (large blocks, per-lane search for that nuclide): identical bits to the
-    oracle for every grid method and both precisions."""
+    oracle for every grid method, both precisions and all three stage
+    shapes."""
     say("lds groups", union_by_material)
     t = synth.random_tables(17, 80, 500, 3, sizes=[70, 33, 5])
     q = synth.random_queries(17, t, 60_000)
@@ -366,10 +378,13 @@ def test_lds_staging_groups(union_by_material):
                                   (64, 2, "band_material"),
                                   (512, 2, "material_energy")):
                 for prec, r in ((xs.XS_FP64, ref), (xs.XS_FP32, ref32)):
-                    out = run(h, E, m, precision=prec, grid=grid, sort=sort,
-                              sort_threshold=0, block_size=bs,
-                              lookups_per_thread=lpt, unroll=1, lds_stage=1)
-                    assert np.array_equal(out, r), (grid, bs, lpt, sort, prec)
+                    for shape in (1, 2, 3):
+                        out = run(h, E, m, precision=prec, grid=grid,
+                                  sort=sort, sort_threshold=0, block_size=bs,
+                                  lookups_per_thread=lpt, unroll=1,
+                                  lds_stage=shape)
+                        assert np.array_equal(out, r), (grid, bs, lpt, sort,
+                                                        prec, shape)
     finally:
         h.close()
 

@@ -58,7 +58,7 @@ def all_valid(calls):
         assert 1 <= c["lpt"] <= 8 and c["u"] in (1, 2, 4)
         assert c["u"] == 1 or c["lpt"] <= 2
         assert c["bs"] <= max_block(c["lpt"], c["u"])
-        assert c["lds"] in (0, 1)
+        assert c["lds"] in (0, 1, 2, 3)
         assert c["lds"] == 0 or (c["lpt"] <= 2 and c["u"] == 1 and
                                  c["bs"] <= 1024 // c["lpt"])
         assert c["wave"] in (0, 1)
@@ -98,8 +98,8 @@ def test_space_size_matches_enumeration():
     n = 0
     for lpt, u in [(l, 1) for l in range(1, 9)] + [(1, 2), (2, 2), (1, 4), (2, 4)]:
         n += sum(1 for b in BLOCKS if b <= max_block(lpt, u))
-    for lpt in (1, 2):  # LDS staging
-        n += sum(1 for b in BLOCKS if b <= 1024 // lpt)
+    for lpt in (1, 2):  # LDS staging, three stage shapes
+        n += 3 * sum(1 for b in BLOCKS if b <= 1024 // lpt)
     n += sum(1 for b in BLOCKS if b <= 256)  # one wave per lookup
     for grids, mult in ((7, 3), (1, 1), (5, 2)):
         cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0)
