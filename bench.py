@@ -356,7 +356,8 @@ def request_stream(args, torch, synth, xs):
 def tuner_study(args, torch, synth, xs):
     """The paper's search against exhaustive search on the tuning space
     (grid method x sort x block x lookups/lane x nuclides in flight x LDS
-    staging, FP32 form) for one batch of the full-size workload.  Every
+    stage shape x wave per lookup, FP32 form) for one batch of the full-size
+    workload.  Every
     configuration is timed once (best of 3 after 1 warm-up, HIP events);
     then the forest search (LCB, kappa 1.96) and uniform random search are
     replayed on that measured table over many seeds, so both see identical
@@ -377,7 +378,7 @@ def tuner_study(args, torch, synth, xs):
     ev = (torch.cuda.Event(enable_timing=True),
           torch.cuda.Event(enable_timing=True))
     keyf = ("grid", "sort", "block_size", "lookups_per_thread", "unroll",
-            "lds_stage")
+            "lds_stage", "wave_per_lookup")
     table = {}
 
     def measure(p, cutoff):
@@ -391,6 +392,8 @@ def tuner_study(args, torch, synth, xs):
             ev[1].synchronize()
             best = min(best, ev[0].elapsed_time(ev[1]))
         table[k] = best
+        if len(table) % 100 == 0:
+            log(f"  {len(table)} configurations timed")
         return best
 
     log(f"tuner study: exhaustive timing of the space at n={n}")
