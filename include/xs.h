@@ -316,16 +316,19 @@ typedef xs_status (*xs_eval_fn)(const xs_params* p, double cutoff_ms,
 xs_status xs_tune_config_default(xs_tune_config* c);
 
 /* Searches the space of (grid method in built_grids & grid_mask) x (sort
- * policy) x (block size 64..1024) x (lookups per lane, nuclides in flight),
- * invalid combinations excluded, calling `eval` for each configuration it
- * picks.  No device call of its own. */
+ * policy) x (block size 64..1024) x (lookups per lane, nuclides in flight,
+ * LDS stage shape, wave per lookup), invalid combinations excluded, calling
+ * `eval` for each configuration it picks; the first is the baseline (hash
+ * grid if built, banded sort, block 256, two nuclides in flight).  No
+ * device call of its own. */
 xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
                          xs_eval_fn eval, void* user, xs_tune_result* result);
 
 /* Tunes xs_lookup_batch for batches of n lookups on the caller's sample
  * (DEVICE d_E / d_mat [n], d_out [n][5] of the precision's type, d_ws at
  * least xs_workspace_size(n) with a sort), timing each configuration with
- * HIP events on `stream`, and records the winner in the handle for the
+ * HIP events on `stream`; the baseline is the untuned default for n, so the
+ * result is never slower than it.  Records the winner in the handle for the
  * batch-size class floor(log2 n): later calls whose fields are XS_AUTO use
  * the tuned value of the nearest class.  Synchronises `stream`. */
 xs_status xs_tune(xs_tables_t tables, int64_t n, const double* d_E,

@@ -146,6 +146,11 @@ void clear_error();
                         "%s failed: %s", #call, hipGetErrorString(e_));   \
   } while (0)
 
+// The library's parameters for a batch of n lookups when none were tuned
+// (every field set; xs_api.hip).
+void untuned_defaults(const xs_tables_s* h, int64_t n, int precision,
+                      xs_params* out);
+
 // Debug mode (xs_debug.hip): resets the current call's words of `counters`
 // and counts the invalid queries among the first n (active ones only when
 // `active` is not null).

@@ -331,8 +331,12 @@ xs_status xs_tune_config_default(xs_tune_config* c) {
   return XS_OK;
 }
 
-xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
-                         xs_eval_fn eval, void* user, xs_tune_result* result) {
+// The search; `baseline`, when given, is the configuration evaluated first
+// (the time-out reference, and what the result can never be worse than).
+static xs_status tune_search(uint32_t built_grids, const xs_tune_config* cfg,
+                             xs_eval_fn eval, void* user,
+                             const xs_params* baseline,
+                             xs_tune_result* result) {
   clear_error();
   if (!cfg || !eval || !result)
     return fail(XS_EINVAL, "config, evaluator and result must not be NULL");
@@ -350,16 +354,21 @@ xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
   if (N == 0) return fail(XS_EINVAL, "the parameter space is empty");
   S.obj.assign(N, std::numeric_limits<double>::quiet_NaN());
 
-  // Baseline: the library default (hash grid if built, banded sort, block
-  // 256, one lookup per lane, two nuclides in flight), else the first
-  // candidate.
+  // Baseline: the given configuration, else the library default for large
+  // batches (hash grid if built, banded sort, block 256, one lookup per
+  // lane, two nuclides in flight); the first candidate if the space does
+  // not hold it.
   xs_params base{};
-  base.grid = (grids & 2u) ? XS_GRID_HASH : ((grids & 1u) ? XS_GRID_NUCLIDE
-                                                          : XS_GRID_UNIONIZED);
-  base.sort = (sorts & 16u) ? XS_SORT_BAND_MATERIAL : XS_SORT_NONE;
-  base.block_size = 256;
-  base.lookups_per_thread = 1;
-  base.unroll = 2;
+  if (baseline) {
+    base = *baseline;
+  } else {
+    base.grid = (grids & 2u) ? XS_GRID_HASH
+                             : ((grids & 1u) ? XS_GRID_NUCLIDE : XS_GRID_UNIONIZED);
+    base.sort = (sorts & 16u) ? XS_SORT_BAND_MATERIAL : XS_SORT_NONE;
+    base.block_size = 256;
+    base.lookups_per_thread = 1;
+    base.unroll = 2;
+  }
   int b0 = 0;
   for (int i = 0; i < N; ++i)
     if (same_choice(S.space[i].p, base)) b0 = i;
@@ -450,6 +459,11 @@ xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
   return XS_OK;
 }
 
+xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
+                         xs_eval_fn eval, void* user, xs_tune_result* result) {
+  return tune_search(built_grids, cfg, eval, user, nullptr, result);
+}
+
 }  // extern "C"
 
 namespace xs {
@@ -535,8 +549,12 @@ xs_status xs_tune(xs_tables_t h, int64_t n, const double* d_E,
                nullptr};
   XS_HIP(hipEventCreate(&d.a));
   XS_HIP(hipEventCreate(&d.b));
+  // The untuned default for this batch is the baseline, so tuning never
+  // returns anything slower than what an untuned call would run.
+  xs_params def;
+  untuned_defaults(h, n, cfg->precision, &def);
   xs_tune_result r{};
-  const xs_status st = xs_tune_search(built, cfg, device_eval, &d, &r);
+  const xs_status st = tune_search(built, cfg, device_eval, &d, &def, &r);
   (void)hipEventDestroy(d.a);
   (void)hipEventDestroy(d.b);
   if (st != XS_OK) return st;

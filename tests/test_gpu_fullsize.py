@@ -103,9 +103,42 @@ def test_fp32_samples_and_bound(full, grid):
               dict(sort="band_material", sort_threshold=0, block_size=256,
                    lookups_per_thread=1, unroll=1, lds_stage=1),
               dict(sort="band_material", sort_threshold=0, block_size=128,
-                   lookups_per_thread=2, unroll=1, lds_stage=1)):
+                   lookups_per_thread=2, unroll=1, lds_stage=1),
+              dict(sort="band_material", sort_threshold=0, block_size=128,
+                   lookups_per_thread=1, unroll=1, lds_stage=2),
+              dict(sort="band_material", sort_threshold=0, block_size=256,
+                   lookups_per_thread=2, unroll=1, lds_stage=3)):
         o2 = run(full, precision=xs.XS_FP32, grid=grid, **k).cpu().numpy()
         assert np.array_equal(o2, o), k
+    full["out32_" + grid] = o
+
+
+@pytest.mark.parametrize("n", [100_000, 1_000_000])
+def test_sparser_prefixes_in_every_kernel(full, n):
+    """The first n lookups of the batch are sparser in energy per material,
+    so wider stage shapes and one wave per lookup are the tuned choices
+    there: every kernel gives the bits of the same lookups in the full
+    batch."""
+    say("prefix", n)
+    if "out32_unionized" not in full:
+        pytest.skip("full FP32 run failed")
+    ref = full["out32_unionized"][:n]
+    for k in (dict(sort="band_material", sort_threshold=0, block_size=64,
+                   lookups_per_thread=1, unroll=1, lds_stage=s)
+              for s in (1, 2, 3)):
+        o = run(full, n=n, precision=xs.XS_FP32, grid="unionized", **k)
+        assert np.array_equal(o.cpu().numpy(), ref), (n, k)
+    for grid in ("unionized", "hash", "nuclide"):
+        for srt in ("none", "band_material"):
+            o = run(full, n=n, precision=xs.XS_FP32, grid=grid, sort=srt,
+                    sort_threshold=0, block_size=128, lookups_per_thread=1,
+                    unroll=1, lds_stage=0, wave_per_lookup=1)
+            assert np.array_equal(o.cpu().numpy(), ref), (n, grid, srt)
+    # untuned defaults at this size
+    o = xs.xs_lookup_batch(full["h"], full["E"][:n], full["m"][:n],
+                           params=xs.xs_params_default(xs.XS_FP32))
+    torch.cuda.synchronize()
+    assert np.array_equal(o.cpu().numpy(), ref)
 
 
 def test_union_by_material_full(full):
