@@ -589,6 +589,26 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
                           hipGetErrorString(e)));
     info.union_size = U;
     info.bytes_union = (size_t)U * 8 + bytes;
+
+    // Logarithmic bins over the union grid (about 32 points per bin): the
+    // union bracket of each bin's lower edge.  Lookups verify the bracket
+    // they find, so the rounding of log and exp never changes a result.
+    const int UB = (int)std::max<int64_t>(1, std::min<int64_t>(U / 32, 1 << 20));
+    const double uln = std::log(u.front());
+    const double uspan = std::log(u.back()) - uln;
+    std::vector<int32_t> uh((size_t)UB + 1);
+    for (int b = 0; b < UB; ++b) {
+      const double edge = std::exp(uln + (double)b * (uspan / UB));
+      const int64_t c = std::upper_bound(u.begin(), u.end(), edge) - u.begin();
+      uh[b] = (int32_t)std::max<int64_t>(c - 1, 0);
+    }
+    uh[UB] = (int32_t)(U - 1);
+    int32_t* uh_dev;
+    if ((st = upload(h, uh.data(), uh.size(), &uh_dev, s))) return cleanup(st);
+    d.UB = UB;
+    d.u_ln_min = uln;
+    d.u_inv_dln = (double)UB / uspan;
+    d.uh = uh_dev;
   }
   hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
   if (e != hipSuccess)

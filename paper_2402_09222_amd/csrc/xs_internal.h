@@ -61,6 +61,12 @@ struct DevTables {
   const int32_t* uidx;       // [U][K], or per material m a block [U][L_m]
                              // at U * moff[m] (union_by_material)
   int32_t union_by_material;
+  // logarithmic bins over the union grid: row uh[b] is the union bracket of
+  // bin b's lower edge (uh[UB] = U - 1), so a lookup searches one bin
+  int32_t UB;                // bins (0 = not built)
+  double u_ln_min;           // ln u[0]
+  double u_inv_dln;          // UB / (ln u[U-1] - ln u[0])
+  const int32_t* uh;         // [UB + 1]
   // debug counters, null unless the handle is in debug mode:
   // [kDbgHashScans] hash searches that left the fast two-interval window,
   // [kDbgHashFull] of those, searches that fell back to full bisection

@@ -173,6 +173,22 @@ struct Locator<XS_GRID_HASH> {
   }
 };
 
+// The union bracket of E (bisect_le over the union grid): the logarithmic
+// bin of E bounds it between two bin edges' brackets, about 32 points apart,
+// and the bracket found there is verified; the rounding of log can only put E
+// in a neighbouring bin, where the verify fails and the whole grid is
+// bisected.  Three or four dependent loads instead of 22 for 4M points.
+__device__ __forceinline__ int union_row(const DevTables& t, double e) {
+  double x = (log(e) - t.u_ln_min) * t.u_inv_dln;
+  x = fmin(fmax(x, 0.0), (double)(t.UB - 1));
+  const int b = (int)x;
+  const int lo = t.uh[b], hi = t.uh[b + 1];
+  const int j = lo + bisect_le(t.u + lo, hi - lo + 1, e);
+  const int U = (int)t.U;
+  const bool ok = (j == 0 || t.u[j] <= e) && (j == U - 1 || e < t.u[j + 1]);
+  return ok ? j : bisect_le(t.u, U, e);
+}
+
 // Row j of the index table: [U][K] (column = nuclide id) or, when built by
 // material, material m's block [U][L_m] (column = position in m's list).
 template <>
@@ -180,7 +196,7 @@ struct Locator<XS_GRID_UNIONIZED> {
   const int32_t* urow;
   int jbase;  // first list position of the material (by-material layout)
   __device__ __forceinline__ void init(const DevTables& t, double e, int m) {
-    init_row(t, bisect_le(t.u, (int)t.U, e), m);
+    init_row(t, union_row(t, e), m);
   }
   // State for union point j (the bracket of E in the union grid).
   __device__ __forceinline__ void init_row(const DevTables& t, int64_t j,
