@@ -492,8 +492,13 @@ def energy_study(args, torch, synth, xs):
     for name, f in objective.items():
         log(f"energy study: tuning for {name}")
 
-        def evaluate(p, cutoff, f=f):
+        done = [0]
+
+        def evaluate(p, cutoff, f=f, done=done):
             sec, joule, _ = measure(call(p), meter, min_seconds=0.25)
+            done[0] += 1
+            if done[0] % 16 == 0:
+                log(f"  {done[0]} configurations measured")
             return f(sec, joule)
         r = xs.xs_tune_search(7, xs.xs_tune_config_default(
             precision=xs.XS_FP32, strategy=xs.XS_TUNE_FOREST,
