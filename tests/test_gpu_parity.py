@@ -243,6 +243,37 @@ def test_hash_bins_indices(cfg1, bins):
     h.close()
 
 
+def test_union_bin_edges(cfg1):
+    """Energies at and next to every edge of the logarithmic bins over the
+    union grid (about 32 union points per bin), where the rounding of log
+    decides the bin: brackets and sums stay the oracle's in every kernel
+    that searches the union grid per lookup."""
+    say("union bin edges")
+    t = cfg1["t"]
+    u = np.unique(t.energy)
+    U = xs.xs_table_info(cfg1["h"])["union_size"]
+    assert U == len(u)
+    UB = max(1, min(U // 32, 1 << 20))
+    uln = np.log(u[0])
+    step = (np.log(u[-1]) - uln) / UB
+    edges = np.exp(uln + np.arange(UB + 1) * step)
+    E = np.concatenate([edges, np.nextafter(edges, 0), np.nextafter(edges, np.inf),
+                        u[::7], np.nextafter(u[::7], 0)])
+    E = E[(E > 0) & np.isfinite(E)]
+    m = (np.arange(len(E)) % t.n_materials).astype(np.int32)
+    ref, idx_ref, off = oracle.lookup(t, E, m, with_index=True)
+    Ed, md = dev(E, torch.float64), dev(m, torch.int32)
+    idx = xs.xs_lookup_indices(cfg1["h"], Ed, md, dev(off, torch.int64),
+                               grid="unionized")
+    torch.cuda.synchronize()
+    assert np.array_equal(idx.cpu().numpy(), idx_ref)
+    for k in (dict(sort="none", lookups_per_thread=1, unroll=2),
+              dict(sort="none", lookups_per_thread=1, unroll=1, lds_stage=0,
+                   wave_per_lookup=1, block_size=128)):
+        out = run(cfg1["h"], Ed, md, grid="unionized", **k)
+        assert np.array_equal(out, ref), k
+
+
 @pytest.mark.parametrize("queue", [xs.XS_QUEUE_COMPACT, xs.XS_QUEUE_PREDICATED])
 @pytest.mark.parametrize("sort", ["none", "material_energy", "band_material"])
 def test_active_mask(cfg1, queue, sort):
