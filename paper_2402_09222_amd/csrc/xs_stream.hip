@@ -16,27 +16,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <limits>
 #include <vector>
 
 #include "xs_lookup_impl.h"
+#include "xs_stream_tiles.h"
 
 namespace xs {
 namespace {
 
 constexpr int kStreamThreads = 256;
-constexpr int kStreamTile = 1024;  // lookups per claimed tile
 constexpr int kPerLane = kStreamTile / kStreamThreads;
-
-struct ReqDev {
-  const double* E;
-  const int32_t* mat;
-  void* out;
-  int64_t n;
-  int64_t tile_begin;  // first global tile of the request
-  int64_t begin;       // first position in the batch's concatenated order
-};
 
 // Tile sort key: material in the high 16 bits, then the top 16 bits of the
 // energy key; lanes without a lookup sort last.
@@ -119,40 +111,51 @@ __device__ __forceinline__ void process_tile(const DevTables& t,
   }
 }
 
-// Request of global tile g: largest r < count with tile_begin <= g.
-__device__ __forceinline__ int request_of(const ReqDev* reqs, int count,
-                                          int64_t g) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (reqs[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Persistent form for request streams: a fixed grid (a few blocks per
-// compute unit) strides over the batch's tiles.  The tile count and the
-// request count are kernel arguments, rewritten in the instantiated graph
-// before every launch, so the loop bound never comes from device memory and
-// every block leaves after at most ceil(tiles / gridDim) tiles.
+// compute unit) strides over the batch's tiles.  Nothing read from device
+// memory bounds a loop: the tile count, the request count, the batch's tag
+// and the largest request size are kernel arguments, rewritten in the
+// instantiated graph before every launch, so every block leaves after at
+// most ceil(tiles / gridDim) tiles whatever the descriptors hold.  A tile
+// whose descriptor fails descriptor_ok (not written for this batch) is
+// skipped without touching the descriptor's pointers and counted in
+// stamps[2 * count + 1], which the host turns into an error.
 template <int GRID, int PREC, int U>
 __global__ __launch_bounds__(kStreamThreads) void k_stream(
     const DevTables t, const ReqDev* __restrict__ reqs, int count,
-    int64_t tiles, unsigned long long* stamps, int64_t ebits_min, int eshift) {
+    int64_t tiles, uint64_t tag, int64_t max_n, unsigned long long* stamps,
+    int64_t ebits_min, int eshift) {
   __shared__ uint32_t skey[kStreamTile];
   __shared__ uint16_t sidx[kStreamTile];
+  __shared__ int s_req;
+  __shared__ int s_ok;
   for (int64_t g = blockIdx.x; g < tiles; g += gridDim.x) {
     const unsigned long long t0 = wall_clock64();
-    const int r = request_of(reqs, count, g);
-    const ReqDev R = reqs[r];
-    process_tile<GRID, PREC, U>(t, R, (g - R.tile_begin) * kStreamTile, skey,
-                                sidx, ebits_min, eshift);
-    __syncthreads();  // the tile's LDS is reused by the next tile
+    // One lane picks and checks the descriptor; the block follows its
+    // verdict, so the barriers inside process_tile are met by every lane.
     if (threadIdx.x == 0) {
-      const unsigned long long t1 = wall_clock64();
-      atomicMin(&stamps[2 * r], t0);
-      atomicMax(&stamps[2 * r + 1], t1);
-      atomicMin(&stamps[2 * count], t0);
+      const int r = request_of(reqs, count, g);
+      s_req = r;
+      s_ok = descriptor_ok(reqs[r], g, tag, max_n) ? 1 : 0;
+    }
+    __syncthreads();
+    const int r = s_req;
+    const bool ok = s_ok != 0;
+    if (ok) {
+      const ReqDev R = reqs[r];
+      process_tile<GRID, PREC, U>(t, R, (g - R.tile_begin) * kStreamTile,
+                                  skey, sidx, ebits_min, eshift);
+    }
+    __syncthreads();  // LDS and s_req / s_ok are rewritten for the next tile
+    if (threadIdx.x == 0) {
+      if (ok) {
+        const unsigned long long t1 = wall_clock64();
+        atomicMin(&stamps[2 * r], t0);
+        atomicMax(&stamps[2 * r + 1], t1);
+        atomicMin(&stamps[2 * count], t0);
+      } else {
+        atomicAdd(&stamps[2 * count + 1], 1ull);
+      }
     }
   }
 }
@@ -182,14 +185,18 @@ __global__ __launch_bounds__(kStreamThreads) void k_requests(
 }
 
 // stamps[2r] = first start (init: max), stamps[2r+1] = last end (init: 0),
-// stamps[2*count] = batch start.
+// stamps[2*count] = batch start, stamps[2*count+1] = tiles skipped because
+// their descriptor was not the batch's (request streams).
 __global__ void k_requests_init(unsigned long long* stamps, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) {
     stamps[2 * i] = ~0ull;
     stamps[2 * i + 1] = 0;
   }
-  if (i == 0) stamps[2 * count] = ~0ull;
+  if (i == 0) {
+    stamps[2 * count] = ~0ull;
+    stamps[2 * count + 1] = 0;
+  }
 }
 
 // Batch-sorted mode, step 1: block b copies tile b of its request into the
@@ -496,15 +503,26 @@ xs_status xs_requests_stats(const void* d_ws, int32_t count, void* stream,
 }  // extern "C"
 
 // ---- request streams: the persistent kernel in a reusable graph ------------
+//
+// Ordering of a submit: the descriptors are written to pinned host memory,
+// copied to the device on the stream object's own upload stream, and the
+// host waits for that copy to complete before it rewrites the graph's
+// kernel arguments and launches the graph on the caller's stream.  The
+// kernel therefore never starts before its descriptors are in device
+// memory, whatever the runtime does to order a copy against a graph launch
+// on one stream; and each descriptor carries the batch's tag, which the
+// kernel checks before it uses the descriptor.
 
 struct xs_stream_s {
   xs_tables_t tables = nullptr;
   xs_params params{};
   hipStream_t user = nullptr;
+  hipStream_t upload = nullptr;  // descriptor copies (host waits for them)
   int32_t max_requests = 0;
   int32_t pending = 0;  // requests of the batch in flight (0 = idle)
+  uint64_t batches = 0; // submitted batches (tag source)
   xs::ReqDev* reqs_dev = nullptr;
-  unsigned long long* stamps_dev = nullptr;  // 2 * max_requests + 1
+  unsigned long long* stamps_dev = nullptr;  // 2 * max_requests + 2
   xs::ReqDev* host = nullptr;                // pinned staging of descriptors
   std::vector<int64_t> sizes;
   hipGraph_t graph = nullptr;
@@ -519,9 +537,11 @@ struct xs_stream_s {
   unsigned long long* a_stamps = nullptr;
   int a_count = 0;
   int64_t a_tiles = 0;
+  uint64_t a_tag = 0;
+  int64_t a_max_n = 0;
   int64_t a_bmin = 0;
   int a_shift = 0;
-  void* run_args[7] = {};
+  void* run_args[9] = {};
   void* init_args[2] = {};
   const void* run_func = nullptr;
 };
@@ -533,6 +553,7 @@ void stream_release(xs_stream_s* s) {
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->done) (void)hipEventDestroy(s->done);
+  if (s->upload) (void)hipStreamDestroy(s->upload);
   if (s->reqs_dev) (void)hipFree(s->reqs_dev);
   if (s->stamps_dev) (void)hipFree(s->stamps_dev);
   if (s->host) (void)hipHostFree(s->host);
@@ -618,11 +639,13 @@ xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
   xs_status st;
   const size_t req_bytes = sizeof(ReqDev) * (size_t)max_requests;
   if ((st = hip(hipMalloc(&s->reqs_dev, req_bytes), "hipMalloc")) ||
-      (st = hip(hipMalloc(&s->stamps_dev, 8 * (2 * (size_t)max_requests + 1)),
+      (st = hip(hipMalloc(&s->stamps_dev, 8 * (2 * (size_t)max_requests + 2)),
                 "hipMalloc")) ||
       (st = hip(hipHostMalloc(&s->host, req_bytes), "hipHostMalloc")) ||
       (st = hip(hipEventCreateWithFlags(&s->done, hipEventDisableTiming),
-                "hipEventCreate")))
+                "hipEventCreate")) ||
+      (st = hip(hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking),
+                "hipStreamCreateWithFlags")))
     return bail(st);
   int dev = 0, cus = 0, khz = 0;
   if ((st = hip(hipGetDevice(&dev), "hipGetDevice")) ||
@@ -637,20 +660,25 @@ xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
   s->blocks = std::max(1, cus) * 4;
   s->clock_khz = khz > 0 ? khz : 100000.0;
 
-  // Kernel arguments live in the handle; the nodes point at them.
+  // Kernel arguments live in the handle; the nodes point at them.  Until the
+  // first submit the run node has no tiles and matches no descriptor.
   s->a_t = h->d;
   s->a_reqs = s->reqs_dev;
   s->a_stamps = s->stamps_dev;
-  s->a_count = 0;
+  s->a_count = 1;
   s->a_tiles = 0;
+  s->a_tag = 0;
+  s->a_max_n = 0;
   energy_key_shift(h, &s->a_bmin, &s->a_shift);
   s->run_args[0] = &s->a_t;
   s->run_args[1] = &s->a_reqs;
   s->run_args[2] = &s->a_count;
   s->run_args[3] = &s->a_tiles;
-  s->run_args[4] = &s->a_stamps;
-  s->run_args[5] = &s->a_bmin;
-  s->run_args[6] = &s->a_shift;
+  s->run_args[4] = &s->a_tag;
+  s->run_args[5] = &s->a_max_n;
+  s->run_args[6] = &s->a_stamps;
+  s->run_args[7] = &s->a_bmin;
+  s->run_args[8] = &s->a_shift;
   s->init_args[0] = &s->a_stamps;
   s->init_args[1] = &s->a_count;
   s->run_func = stream_func(p);
@@ -678,35 +706,44 @@ xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
   if (count < 1 || count > s->max_requests)
     return fail(XS_EINVAL, "count must be in [1, %d]", s->max_requests);
   if (!reqs) return fail(XS_EINVAL, "reqs is NULL");
-  int64_t tiles = 0, begin = 0;
+  int64_t tiles = 0, begin = 0, max_n = 0;
   for (int i = 0; i < count; ++i) {
     const xs_request& r = reqs[i];
     if (r.n < 0 || r.n > 0x7fffffffLL)
       return fail(XS_EINVAL, "request %d: n out of range", i);
     if (r.n > 0 && (!r.d_E || !r.d_mat || !r.d_out))
       return fail(XS_EINVAL, "request %d: a pointer is NULL", i);
-    tiles += (r.n + kStreamTile - 1) / kStreamTile;
+    tiles += tiles_of(r.n);
     begin += r.n;
+    max_n = std::max<int64_t>(max_n, r.n);
   }
   if (tiles > 0x7fffffffLL) return fail(XS_EINVAL, "batch too large");
-  // The previous batch has been waited for, so the staging buffer is free.
+  // A tag no earlier batch of any stream object in the process used.
+  static std::atomic<uint64_t> batches_in_process{0};
+  const uint64_t tag = 0x9e3779b97f4a7c15ull * (++batches_in_process);
+  ++s->batches;
+  // The previous batch has been waited for, so the staging buffer and the
+  // device descriptors are free.
   s->sizes.assign(count, 0);
   tiles = 0;
   begin = 0;
   for (int i = 0; i < count; ++i) {
     const xs_request& r = reqs[i];
-    s->host[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles, begin};
-    tiles += (r.n + kStreamTile - 1) / kStreamTile;
+    s->host[i] = ReqDev{r.d_E, r.d_mat, r.d_out, r.n, tiles, begin, tag, 0};
+    tiles += tiles_of(r.n);
     begin += r.n;
     s->sizes[i] = r.n;
   }
+  XS_HIP(hipMemcpyAsync(s->reqs_dev, s->host, sizeof(ReqDev) * count,
+                        hipMemcpyHostToDevice, s->upload));
+  XS_HIP(hipStreamSynchronize(s->upload));
   s->a_count = count;
   s->a_tiles = tiles;
+  s->a_tag = tag;
+  s->a_max_n = max_n;
   const hipKernelNodeParams ip = init_params(s), rp = run_params(s);
   XS_HIP(hipGraphExecKernelNodeSetParams(s->exec, s->init_node, &ip));
   XS_HIP(hipGraphExecKernelNodeSetParams(s->exec, s->run_node, &rp));
-  XS_HIP(hipMemcpyAsync(s->reqs_dev, s->host, sizeof(ReqDev) * count,
-                        hipMemcpyHostToDevice, s->user));
   XS_HIP(hipGraphLaunch(s->exec, s->user));
   XS_HIP(hipEventRecord(s->done, s->user));
   s->pending = count;
@@ -721,9 +758,13 @@ xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
   XS_HIP(hipEventSynchronize(s->done));
   const int count = s->pending;
   s->pending = 0;
-  std::vector<unsigned long long> st(2 * (size_t)count + 1);
+  std::vector<unsigned long long> st(2 * (size_t)count + 2);
   XS_HIP(hipMemcpy(st.data(), s->stamps_dev, 8 * st.size(),
                    hipMemcpyDeviceToHost));
+  if (st[2 * (size_t)count + 1] != 0)
+    return fail(XS_EHIP, "%llu tiles of the batch met request descriptors "
+                "that were not this batch's and were skipped (their outputs "
+                "are not written)", st[2 * (size_t)count + 1]);
   const double us_per_tick = 1000.0 / s->clock_khz;
   const unsigned long long t0 = st[2 * (size_t)count];
   unsigned long long tmax = t0;

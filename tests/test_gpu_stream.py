@@ -11,17 +11,7 @@ import oracle
 import synth
 
 torch = pytest.importorskip("torch")
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason=(
-        "the first run of these tests on the GPU (a stream-captured graph "
-        "whose blocks claimed tiles with an atomic counter) went silent for "
-        "180 s inside test_stream_matches_oracle[nuclide-1-0] and was "
-        "killed; no cause has been shown, and the rebuilt path (graph built "
-        "node by node, striding persistent grid, counts as kernel arguments) "
-        "removes differences without a shown cause, so the case stays off "
-        "the GPU")),
-]
+pytestmark = pytest.mark.gpu
 
 from paper_2402_09222_amd import xs  # noqa: E402
 
