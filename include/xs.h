@@ -347,10 +347,13 @@ xs_status xs_set_tuned(xs_tables_t tables, int64_t n, const xs_params* p);
  * kernel call, and with short kernels launches and queue-count transfers to
  * the host leave bubbles).  The graph [reset times] -> [persistent kernel]
  * is built once; before each launch its kernel arguments (request and tile
- * counts) are rewritten.  The kernel's fixed grid strides over the batch's
- * 1024-lookup tiles; each block sorts a tile in LDS by material and energy,
- * looks it up, and stamps the request's first and last tile with the device
- * wall clock.  Results equal xs_lookup_batch's bit for bit. */
+ * counts, the batch's tag, the largest request size) are rewritten.  The
+ * kernel's fixed grid strides over the batch's 1024-lookup tiles, so no loop
+ * bound comes from device memory; each block checks the tile's descriptor
+ * (the batch's tag, a size within the host's bound, the tile inside the
+ * request), sorts the tile in LDS by material and energy, looks it up, and
+ * stamps the request's first and last tile with the device wall clock.
+ * Results equal xs_lookup_batch's bit for bit. */
 typedef struct xs_stream_s* xs_stream_t;
 
 typedef struct {
@@ -377,14 +380,18 @@ xs_status xs_stream_create(xs_tables_t tables, const xs_params* params,
                            xs_stream_t* out);
 
 /* Enqueues one batch (HOST array of count descriptors, read during the call)
- * on the stream: descriptor upload, then one graph launch.  One batch may be
- * in flight per stream object; XS_EINVAL if the previous one was not
- * waited for. */
+ * on the stream: the descriptors are copied to the device on the stream
+ * object's own upload stream and the host waits for that copy (no wait on
+ * the caller's stream), then the graph is launched on the caller's stream.
+ * One batch may be in flight per stream object; XS_EINVAL if the previous
+ * one was not waited for. */
 xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
                            int32_t count);
 
 /* Waits for the batch and fills stats[count] (may be NULL) and the batch's
- * device makespan in microseconds (may be NULL). */
+ * device makespan in microseconds (may be NULL).  XS_EHIP if any tile met a
+ * descriptor that was not written for this batch (its outputs are then not
+ * written). */
 xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
                          double* makespan_us);
 
