@@ -17,7 +17,8 @@ lookup (section 5.1 names the operation only), so the pins are:
   bound;
 * the FP32 form stays within its error bound of the FP64 result, also on a
   sum of many equal terms where uncompensated FP32 summation fails;
-* a hand-worked example (tests/golden/worked_example.txt).
+* a hand-worked example (tests/golden/worked_example.txt), and one of the
+  FP32 form with exact expected bits (tests/golden/worked_example_f32.txt).
 """
 from __future__ import annotations
 
@@ -317,8 +318,14 @@ def pin_f32_skewed_interval(lib):
     assert np.all(np.abs(f32 - ref) <= 9 * U32 * ref)
 
 
+def _num(v: str) -> float:
+    """A decimal or hexadecimal (0x1.8p-1) floating-point literal."""
+    return float.fromhex(v) if "0x" in v.lower() else float(v)
+
+
 def read_worked_example(path: str = None):
-    """Parse tests/golden/worked_example.txt."""
+    """Parse tests/golden/worked_example.txt (or another file of that
+    format, such as worked_example_f32.txt)."""
     path = path or os.path.join(GOLDEN, "worked_example.txt")
     grids, xs, mats, queries = [], [], [], []
     for line in open(path):
@@ -327,17 +334,17 @@ def read_worked_example(path: str = None):
             continue
         kind, *rest = line.split()
         if kind == "nuclide":
-            grids.append([float(v) for v in rest])
+            grids.append([_num(v) for v in rest])
             xs.append([])
         elif kind == "point":
-            xs[-1].append([float(v) for v in rest])
+            xs[-1].append([_num(v) for v in rest])
         elif kind == "material":
             ids, dens = rest[0].split(","), rest[1].split(",")
-            mats.append(([int(v) for v in ids], [float(v) for v in dens]))
+            mats.append(([int(v) for v in ids], [_num(v) for v in dens]))
         elif kind == "query":
-            e, m = float(rest[0]), int(rest[1])
+            e, m = _num(rest[0]), int(rest[1])
             idx = [int(v) for v in rest[2].split(",")]
-            want = [float(v) for v in rest[3:8]]
+            want = [_num(v) for v in rest[3:8]]
             queries.append((e, m, idx, want))
     offs = np.zeros(len(grids) + 1, np.int64)
     offs[1:] = np.cumsum([len(g) for g in grids])
@@ -360,6 +367,29 @@ def pin_worked_example(lib):
         assert list(out[r]) == want, (e, mm, list(out[r]), want)
 
 
+def pin_f32_worked_example(lib):
+    """The hand-worked FP32 example (tests/golden/worked_example_f32.txt):
+    dyadic tables whose channel values and densities carry bits beyond
+    FP32's significand, so rounding X and rho to FP32 before the products,
+    the ties to even and the Kahan compensation each show in the expected
+    bits of the sums."""
+    t, queries = read_worked_example(
+        os.path.join(GOLDEN, "worked_example_f32.txt"))
+    E = np.array([q[0] for q in queries])
+    m = np.array([q[1] for q in queries], np.int32)
+    got = oracle.lookup_f32(t, E, m, lib=lib)
+    _, idx, off = oracle.lookup(t, E, m, with_index=True, lib=lib)
+    for r, (e, mm, want_idx, want) in enumerate(queries):
+        assert list(idx[off[r]:off[r + 1]]) == want_idx, (e, mm)
+        w = np.array(want, dtype=np.float64)
+        assert np.array_equal(w.astype(np.float32).astype(np.float64), w), \
+            "an expected value is not an FP32 number"
+        assert np.array_equal(got[r].view(np.uint32),
+                              w.astype(np.float32).view(np.uint32)), \
+            (e, mm, [float(x).hex() for x in got[r]],
+             [float(x).hex() for x in w])
+
+
 def pin_invalid_inputs(lib):
     """E not finite or not > 0, or m out of range: NaN outputs, index -1."""
     t = synth.random_tables(20, 3, 10, 2, sizes=[2, 3])
@@ -377,7 +407,7 @@ ALL_PINS = [
     pin_clamp, pin_affine, pin_constant, pin_midpoint, pin_density_scaling,
     pin_additivity, pin_exact_rational, pin_numpy_interp, pin_f32_bound,
     pin_f32_many_terms, pin_f32_skewed_interval, pin_worked_example,
-    pin_invalid_inputs,
+    pin_f32_worked_example, pin_invalid_inputs,
 ]
 
 

@@ -449,3 +449,52 @@ def test_concurrent_streams_share_tables(cfg1):
                 cur.wait_stream(s)
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), ref), (prec, rep)
+
+
+@pytest.mark.parametrize("golden", ["worked_example.txt",
+                                    "worked_example_f32.txt"])
+def test_worked_examples_exact(golden):
+    """The hand-worked examples (tests/golden/) through every grid method and
+    kernel family: the FP64 file's sums in FP64, the FP32 file's exact bits
+    in the FP32 form, and every bracket as derived."""
+    import os
+    from tests import pins
+    t, queries = pins.read_worked_example(
+        os.path.join(pins.GOLDEN, golden))
+    prec = xs.XS_FP32 if golden.endswith("_f32.txt") else xs.XS_FP64
+    # every query repeated so blocks of every kernel fill up
+    reps = 300
+    E1 = np.array([q[0] for q in queries])
+    m1 = np.array([q[1] for q in queries], np.int32)
+    E_np, m_np = np.tile(E1, reps), np.tile(m1, reps)
+    want = np.tile(np.array([q[3] for q in queries]), (reps, 1))
+    E, m = dev(E_np, torch.float64), dev(m_np, torch.int32)
+    h = xs.xs_create_tables(t, ALL_FLAGS, 7)
+    try:
+        shapes = [dict(sort="none", block_size=256, lookups_per_thread=1,
+                       unroll=1),
+                  dict(sort="material_energy", sort_threshold=0,
+                       block_size=128, lookups_per_thread=2, unroll=2),
+                  dict(sort="band_material", sort_threshold=0, block_size=128,
+                       lookups_per_thread=1, unroll=1, lds_stage=1),
+                  dict(sort="band_material", sort_threshold=0, block_size=64,
+                       lookups_per_thread=1, unroll=1, lds_stage=3),
+                  dict(sort="none", block_size=128, lookups_per_thread=1,
+                       unroll=1, lds_stage=0, wave_per_lookup=1)]
+        for grid in ("nuclide", "hash", "unionized"):
+            for k in shapes:
+                out = run(h, E, m, precision=prec, grid=grid, **k)
+                if prec == xs.XS_FP32:
+                    ok = np.array_equal(out.view(np.uint32),
+                                        want.astype(np.float32).view(np.uint32))
+                else:
+                    ok = np.array_equal(out, want)
+                assert ok, (golden, grid, k)
+            off = oracle.index_offsets(t, m_np)
+            idx = xs.xs_lookup_indices(h, E, m, dev(off, torch.int64),
+                                       grid=grid)
+            torch.cuda.synchronize()
+            want_idx = np.concatenate([q[2] for q in queries] * reps)
+            assert np.array_equal(idx.cpu().numpy(), want_idx), (golden, grid)
+    finally:
+        h.close()

@@ -51,6 +51,12 @@ MUTANTS = [
     ("f32_g_in_fp32", "const float g32 = (float)(1.0 - f);",
      "const float g32 = 1.0f - f32;"),
     ("f32_drop_density", "const float term = rho * sigma;", "const float term = sigma;"),
+    ("f32_density_in_fp64", "const float rho = (float)t->mat_density[j];",
+     "const double rho = t->mat_density[j];"),
+    ("f32_x_unrounded_product", "const float b = f32 * (float)hi[c];",
+     "const float b = (float)(f32 * hi[c]);"),
+    ("f32_interpolate_in_fp64", "const float sigma = a + b;",
+     "const float sigma = (float)((double)(1.0 - f) * lo[c] + f * hi[c]);"),
     ("invalid_not_nan", "for (int c = 0; c < XSO_CHANNELS; ++c) out[c] = NAN;",
      "for (int c = 0; c < XSO_CHANNELS; ++c) out[c] = 0.0;"),
 ]
