@@ -9,9 +9,13 @@ log-uniform energies and uniform materials (see synth.workloads).
 Two forms are timed: the plain FP64 lookup (per-nuclide bisection, no sort,
 256-lane blocks, one lookup per lane) and the FP32 form with parameters
 chosen by the library's tuner; `value` is the latter.  The JSON line carries
-the dominant kernel's roofline (algorithmic bytes per lookup x lookups per
-launch / average kernel time from HIP events on the launch stream) and the
-serial CPU oracle's rate on a bounded sample of the same queries.
+the dominant kernel's roofline (algorithmic flops or bytes per launch /
+average kernel time from HIP events on the launch stream, against the
+vendor peaks, with the issue ceiling and the demand and measured HBM
+figures beside it), the serial CPU oracle's rate (best of 5, on one thread
+and on every thread of the process's CPU share) and the comparison of both
+timed outputs with the oracle on every lookup of the batch; the run exits
+with status 1 if either differs beyond its bar.
 """
 from __future__ import annotations
 
@@ -28,14 +32,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-# Vector ALU issue for the lookup's arithmetic: 256 compute units x 64 lanes
-# x 2.4 GHz = 39.3e12 operations/s.  The vendor's 157.3 TFLOP/s (FP32) counts
-# packed two-wide FMAs and 78.6 (FP64) FMAs; the lookup may use neither (its
-# products and sums must round separately to stay exact, and packed FP32 code
-# generation is off), so each operation is one flop at one lane-issue.
-ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+# Vendor vector peaks (TFLOP/s): FP32 157.3 and FP64 78.6.  They count a
+# fused multiply-add as two flops and, for FP32, packed two-wide issue.
+VENDOR_PEAK_TFLOPS = {0: 78.6, 1: 157.3}
+# The issue ceiling of the lookup's own arithmetic: 256 compute units x 64
+# lanes x 2.4 GHz = 39.3e12 operations/s.  The lookup's products and sums
+# must round separately (no fused multiply-add) and packed FP32 code
+# generation is off, so each of its operations takes one lane-issue.
+ISSUE_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 METRIC = ("macro-XS lookups/s (FP64 plain vs FP32 autotuned) + % HBM "
           "roofline, 1 MI355X")
+# Parity bars: FP64 relative error per channel, FP32 form against FP64.
+TOL_FP64 = 1e-12
+TOL_FP32 = 2e-6
 
 
 def log(*a):
@@ -64,33 +73,49 @@ def flops_per_pair(precision: int) -> float:
 
 def roofline(n: int, nbar: float, precision: int, kernel_ms: float,
              traffic) -> dict:
-    """Roofline of one lookup kernel.  Two ceilings apply: HBM bandwidth
-    against the algorithmic bytes, and vector ALU issue against the
-    algorithmic flops.  Sorted and LDS-staged lookups serve most of their
-    bytes from caches (demand above the HBM peak), so the bound is the ALU
-    one when the measured fabric traffic (or, without a measurement, the
-    demand rate) leaves it the larger fraction."""
+    """Roofline of one lookup kernel from its average launch time.
+
+    `achieved` is always algorithmic work per launch / kernel time.  The
+    ALU view reports the algorithmic flops against the vendor peak of the
+    precision (the primary fraction) and against the issue ceiling of
+    non-fused, non-packed operations.  The HBM view reports the algorithmic
+    bytes as *demand* (above 1 means the demand is served from caches) and,
+    when counters were taken, the measured HBM traffic.  The bound is the
+    ALU one when its issue fraction exceeds the memory fraction (measured
+    traffic, else the demand when it is at most 1)."""
     sec = kernel_ms * 1e-3
     B = bytes_per_lookup(precision, nbar)
-    hbm_ach = n * B / sec / 1e9
+    demand = n * B / sec / 1e9
     F = flops_per_pair(precision)
     alu_ach = n * nbar * F / sec / 1e12
-    alu_frac = alu_ach / ALU_PEAK_TFLOPS
-    hbm = {"achieved": hbm_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": hbm_ach / HBM_PEAK_GBS, "bytes_per_lookup": B}
-    alu = {"achieved": alu_ach, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-           "frac": alu_frac, "flops_per_pair": F, "pairs": n * nbar}
+    vendor = VENDOR_PEAK_TFLOPS[precision]
+    hbm = {"peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "demand_bytes_per_lookup": B, "demand_gbs": demand,
+           "demand_frac": demand / HBM_PEAK_GBS,
+           "demand_note": "algorithmic bytes / kernel time; above 1 the "
+                          "demand is served from caches, not HBM"}
+    alu = {"unit": "TFLOP/s", "flops_per_pair": F, "pairs": n * nbar,
+           "achieved": alu_ach, "vendor_peak": vendor,
+           "vendor_frac": alu_ach / vendor,
+           "issue_peak": ISSUE_PEAK_TFLOPS,
+           "issue_frac": alu_ach / ISSUE_PEAK_TFLOPS,
+           "issue_note": "one non-fused, non-packed operation per lane and "
+                         "cycle on 256 CUs at 2.4 GHz"}
     if traffic is not None:
+        hbm["measured_bytes_per_launch"] = traffic
         hbm["measured_gbs"] = traffic / sec / 1e9
         hbm["measured_frac"] = hbm["measured_gbs"] / HBM_PEAK_GBS
         mem_frac = hbm["measured_frac"]
     else:
-        mem_frac = hbm["frac"] if hbm["frac"] <= 1.0 else 0.0
-    main = alu if alu_frac >= mem_frac else hbm
-    out = {"bound": "alu" if main is alu else "hbm",
-           "achieved": main["achieved"], "peak": main["peak"],
-           "unit": main["unit"], "frac": main["frac"], "traffic": traffic,
-           "kernel_ms": kernel_ms, "hbm": hbm, "alu": alu}
+        mem_frac = hbm["demand_frac"] if hbm["demand_frac"] <= 1.0 else 0.0
+    if alu["issue_frac"] >= mem_frac:
+        out = {"bound": "alu", "achieved": alu_ach, "peak": vendor,
+               "unit": "TFLOP/s", "frac": alu_ach / vendor}
+    else:
+        out = {"bound": "hbm", "achieved": demand, "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": demand / HBM_PEAK_GBS}
+    out.update({"traffic": traffic, "kernel_ms": kernel_ms, "hbm": hbm,
+                "alu": alu})
     return out
 
 
@@ -164,31 +189,110 @@ def kernel_time(xs, h, fn, calls: int) -> dict:
             "ms_total": prof["ms_total"] / c, "calls": prof["calls"]}
 
 
-def cpu_cores() -> int:
+def host_cpus() -> dict:
+    """The host's CPUs as this process sees them: `nproc` (all online CPUs),
+    `affinity` (the CPUs this process may run on), `quota` (the cgroup CPU
+    quota in CPUs, None when unlimited or unreadable), `threads` (what the
+    CPU baseline uses: the affinity set, capped by the quota) and the CPU
+    model name."""
+    nproc = os.cpu_count() or 1
     try:
-        n = len(os.sched_getaffinity(0))
+        aff = len(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(16, n))
+        aff = nproc
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(period)
+    except (OSError, ValueError):
+        try:
+            q = int(open("/sys/fs/cgroup/cpu/cpu.cfs_quota_us").read())
+            period = int(open("/sys/fs/cgroup/cpu/cpu.cfs_period_us").read())
+            if q > 0:
+                quota = q / period
+        except (OSError, ValueError):
+            pass
+    threads = aff
+    if quota is not None:
+        threads = max(1, min(threads, int(quota)))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": nproc, "affinity": aff, "quota": quota,
+            "threads": threads, "model": model}
 
 
-def cpu_baseline(tables, q, seconds: float) -> dict:
+def cpu_baseline(tables, q, seconds: float):
+    """The serial oracle as it stands (gcc -O2), timed best of 5 on one
+    thread and on every thread the process may use (each thread runs the
+    unmodified serial routine on a contiguous slice).  Samples are the
+    first lookups of the batch, sized so the ten runs take about `seconds`.
+    Returns (baseline dict, the oracle's FP64 output when the all-thread
+    sample was the whole batch, else None)."""
     import oracle
     ot = oracle.OracleTables(tables)
-    cores = cpu_cores()
+    host = host_cpus()
+    T = host["threads"]
     probe = min(len(q), 4000)
     t0 = time.perf_counter()
     oracle.lookup(ot, q.E[:probe], q.mat[:probe])
     rate1 = probe / max(time.perf_counter() - t0, 1e-9)
-    n = int(min(len(q), max(probe, rate1 * cores * seconds)))
-    t0 = time.perf_counter()
-    oracle.lookup(ot, q.E[:n], q.mat[:n], threads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "lookups/s", "cores": cores,
+
+    def best_of(n, threads, reps=5):
+        times, out = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = oracle.lookup(ot, q.E[:n], q.mat[:n], threads=threads)
+            times.append(time.perf_counter() - t0)
+        return n / min(times), n / float(np.median(times)), out
+
+    # about 70 % of the budget to the all-thread runs, 30 % to one thread
+    n_all = int(min(len(q), max(probe, rate1 * T * 0.7 * seconds / 5)))
+    n_one = int(min(len(q), max(probe, rate1 * 0.3 * seconds / 5)))
+    best_all, med_all, out_all = best_of(n_all, T)
+    best_one, med_one, _ = best_of(n_one, 1)
+    base = {"value": best_all, "unit": "lookups/s", "cores": T,
             "kind": "oracle",
-            "sample": f"first {n} of the {len(q)} lookups, serial oracle "
-                      f"(gcc -O2) on {cores} threads, each a contiguous slice; "
-                      f"{dt:.1f} s"}
+            "sample": f"first {n_all} of the {len(q)} lookups, serial oracle "
+                      f"(gcc -O2) on {T} threads, each a contiguous slice; "
+                      f"best of 5 (median {med_all:.4g}/s)",
+            "single_thread": {"value": best_one, "median": med_one,
+                              "sample": f"first {n_one} lookups, best of 5"},
+            "host": host}
+    return base, (out_all if n_all == len(q) else None)
+
+
+def _rel_stats(got, ref):
+    """Per-channel max and mean of |got - ref| / ref (ref > 0)."""
+    rel = np.abs(got.astype(np.float64) - ref) / ref
+    return ([float(x) for x in rel.max(axis=0)],
+            [float(x) for x in rel.mean(axis=0)])
+
+
+def parity_fp64(got, ref) -> dict:
+    """The FP64 lookup against the FP64 oracle: per-channel relative error
+    (bar 1e-12) and how many values are bit-identical."""
+    mx, mean = _rel_stats(got, ref)
+    same = int(np.count_nonzero(got == ref))
+    return {"max_rel": mx, "mean_rel": mean, "bit_identical": same,
+            "values": int(got.size), "bar": TOL_FP64,
+            "ok": bool(max(mx) <= TOL_FP64)}
+
+
+def parity_fp32(got, ref32, ref64) -> dict:
+    """The FP32 form against the oracle's FP32 form (bit for bit) and
+    against the FP64 oracle (per-channel relative error, bar 2e-6)."""
+    mx, mean = _rel_stats(got, ref64)
+    bad = int(np.count_nonzero(got.view(np.uint32) != ref32.view(np.uint32)))
+    return {"max_rel": mx, "mean_rel": mean, "mismatches_vs_fp32_form": bad,
+            "values": int(got.size), "bar": TOL_FP32,
+            "ok": bool(bad == 0 and max(mx) <= TOL_FP32)}
 
 
 def _pctl(v, q):
@@ -270,12 +374,15 @@ def sweep_in_flight(args, torch, synth, xs):
 def request_stream(args, torch, synth, xs):
     """Config 5: an uneven stream of requests (sizes log-uniform in
     [1e3, 1e6], energies 70 % log-uniform and 30 % from narrow peaks) served
-    by one xs_lookup_requests call over the whole batch (batch-sorted: one
+    by the persistent graph-launched kernel (xs_stream_*, one graph launch
+    for the whole batch), by one xs_lookup_requests call (batch-sorted: one
     gathered, sorted queue; tile-sorted: one launch, tiles sorted in LDS),
-    against one xs_lookup_batch launch per request with parameters tuned per
-    size class.  A request's latency in the one-call forms runs from its
+    and by one xs_lookup_batch launch per request with parameters tuned per
+    size class.  A request's latency in the one-launch forms runs from its
     first tile's start to its last tile's end (device wall clock); per
-    launch it is the HIP event time of its call."""
+    launch it is the HIP event time of its call.  Every form's output is
+    compared with the per-request launches' bit for bit, and those with the
+    oracle's FP32 form on 200,000 sampled lookups."""
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
              xs.XS_BUILD_UNION_BY_MATERIAL)
@@ -337,19 +444,64 @@ def request_stream(args, torch, synth, xs):
                         "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
         return best
 
+    def snapshot():
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    out_launch = snapshot()  # the per-request launches' results
     p_batch = xs.xs_resolve_params(h, total, p_auto)
     p_tile = xs.xs_params_default(xs.XS_FP32)
     p_tile.sort = xs.XS_SORT_NONE
     p_tile = xs.xs_resolve_params(h, total, p_tile)
+    out.fill_(-1.0)
     res_batch = one_call(p_batch)
+    same = {"one_call_batch_sorted": bool(np.array_equal(snapshot(), out_launch))}
+    out.fill_(-1.0)
     res_tile = one_call(p_tile)
-    print(json.dumps({"config": "uneven request stream", "requests": len(reqs),
-                      "lookups": total, "per_request_launches": best_launch,
-                      "one_call_batch_sorted": res_batch,
-                      "one_call_tile_sorted": res_tile,
-                      "batch_params": p_batch.as_dict(),
-                      "tile_params": p_tile.as_dict()}), flush=True)
+    same["one_call_tile_sorted"] = bool(np.array_equal(snapshot(), out_launch))
+
+    # The persistent kernel: one graph launch per batch of requests.
+    stream = xs.xs_stream_create(h, p_auto, max_requests=len(reqs))
+    p_stream = xs.xs_stream_params(stream)
+    out.fill_(-1.0)
+    res_stream = None
+    for rep in range(max(1, args.steps // 5) + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs.xs_stream_submit(stream, reqs)
+        stats, makespan = xs.xs_stream_wait(stream)
+        wall = time.perf_counter() - t0
+        lat = [r["latency_us"] for r in stats]
+        if rep > 0 and (res_stream is None or wall < res_stream["wall_s"]):
+            res_stream = {"wall_s": wall, "lookups_per_s": total / wall,
+                          "device_makespan_us": makespan,
+                          "device_lookups_per_s": total / (makespan * 1e-6),
+                          "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
+    same["persistent_stream"] = bool(np.array_equal(snapshot(), out_launch))
+    stream.close()
+
+    # The per-request launches against the oracle's FP32 form on a sample.
+    import oracle
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(total, size=min(total, 200_000), replace=False))
+    ref32 = oracle.lookup_f32(t, q.E[pick], q.mat[pick],
+                              threads=host_cpus()["threads"])
+    oracle_ok = bool(np.array_equal(out_launch[pick], ref32))
+    line = {"config": "uneven request stream", "requests": len(reqs),
+            "lookups": total, "per_request_launches": best_launch,
+            "persistent_stream": res_stream,
+            "one_call_batch_sorted": res_batch,
+            "one_call_tile_sorted": res_tile,
+            "batch_params": p_batch.as_dict(),
+            "tile_params": p_tile.as_dict(),
+            "stream_params": p_stream.as_dict(),
+            "bit_identical_to_per_request_launches": same,
+            "per_request_launches_equal_oracle_on_sample": oracle_ok}
+    print(json.dumps(line), flush=True)
     h.close()
+    if not (oracle_ok and all(same.values())):
+        log("PARITY FAILURE in the request-stream forms")
+        return 1
     return 0
 
 
@@ -635,8 +787,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--bins", type=int, default=8192)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0,
+                    help="budget of the CPU baseline's ten timed runs")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip comparing the timed outputs with the oracle")
     ap.add_argument("--no-union", action="store_true",
                     help="skip the 5.7 GB unionized index table")
     ap.add_argument("--params", type=str, default=None,
@@ -732,23 +887,25 @@ def main(argv=None):
 
         def fn():
             xs.xs_lookup_batch(h, E, m, out=out, params=params, workspace=ws)
-        return fn
+        return fn, out
 
     def measure(params):
         params = xs.xs_resolve_params(h, n, params)
-        fn = runner(params)
+        fn, out = runner(params)
         sec = time_steps(fn, args.steps, args.warmup)
         kt = kernel_time(xs, h, fn, max(args.steps, 3))
         kname = kernel_name(params)
         traffic = measured_traffic(kname, params.block_size, n)
         rl = roofline(n, nbar, params.precision, kt["ms_lookup"], traffic)
         rl["kernel"] = kname
+        torch.cuda.synchronize()
         return {
             "value": n / sec, "ms_per_step": sec * 1e3,
             "params": params.as_dict(), "kernel_ms": kt, "roofline": rl,
-        }
+        }, out.cpu().numpy()
 
     plain = tuned = None
+    out_plain = out_tuned = None
     if args.only in (None, "plain"):
         p_plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
                                  block_size=256, lookups_per_thread=1,
@@ -756,7 +913,7 @@ def main(argv=None):
                                  sort_threshold=xs.INT64_MAX,
                                  queue=xs.XS_QUEUE_COMPACT)
         log("timing plain FP64")
-        plain = measure(p_plain)
+        plain, out_plain = measure(p_plain)
         log(f"plain FP64: {plain['value']:.4g} lookups/s, "
             f"{plain['ms_per_step']:.3f} ms/step")
     tune_report = None
@@ -782,17 +939,38 @@ def main(argv=None):
             # caller passing automatic parameters would
             p32 = xs.xs_resolve_params(h, n, xs.xs_params_default(xs.XS_FP32))
         log("timing FP32 form with", p32.as_dict())
-        tuned = measure(p32)
+        tuned, out_tuned = measure(p32)
         tuned["tuner"] = tune_report
         log(f"FP32 tuned: {tuned['value']:.4g} lookups/s, "
             f"{tuned['ms_per_step']:.3f} ms/step")
 
     head = tuned or plain
     cpu = None
+    ref64 = None
     if not args.no_cpu:
         log("timing the CPU oracle")
-        cpu = cpu_baseline(t, q, args.cpu_seconds)
-        log(f"CPU oracle: {cpu['value']:.4g} lookups/s on {cpu['cores']} cores")
+        cpu, ref64 = cpu_baseline(t, q, args.cpu_seconds)
+        log(f"CPU oracle: {cpu['value']:.4g} lookups/s on {cpu['cores']} "
+            f"threads, {cpu['single_thread']['value']:.4g} on one "
+            f"({cpu['host']['model']}, nproc {cpu['host']['nproc']})")
+
+    # The timed outputs against the oracle on every lookup of the batch.
+    parity = None
+    if not args.no_check:
+        import oracle
+        threads = host_cpus()["threads"]
+        log("checking the timed outputs against the oracle")
+        if ref64 is None:
+            ref64 = oracle.lookup(t, q.E, q.mat, threads=threads)
+        parity = {}
+        if out_plain is not None:
+            parity["plain_fp64"] = parity_fp64(out_plain, ref64)
+        if out_tuned is not None:
+            ref32 = oracle.lookup_f32(t, q.E, q.mat, threads=threads)
+            parity["tuned_fp32"] = parity_fp32(out_tuned, ref32, ref64)
+        for k, v in parity.items():
+            log(f"parity {k}: ok={v['ok']} max rel per channel "
+                + " ".join(f"{x:.3g}" for x in v["max_rel"]))
 
     line = {
         "metric": METRIC,
@@ -817,6 +995,7 @@ def main(argv=None):
         },
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
+        "parity": parity,
         "plain_fp64": plain,
         "tuned_fp32": tuned,
     }
@@ -824,6 +1003,9 @@ def main(argv=None):
         line["fp32_tuned_over_fp64_plain"] = tuned["value"] / plain["value"]
     print(json.dumps(line), flush=True)
     h.close()
+    if parity is not None and not all(v["ok"] for v in parity.values()):
+        log("PARITY FAILURE: the timed outputs differ from the oracle")
+        return 1
     return 0
 
 
