@@ -1,11 +1,17 @@
 """Full-size synthetic workload (355 nuclides x 11,303 points, 12 materials,
 10M lookups) in the launch shapes the benchmark times.
 
-The oracle computes sampled lookups one by one; the whole output is checked
-through properties that hold at any size: every grid method, sort policy and
-launch shape gives bit-identical sums within one precision, and the FP32 form
-stays within 2e-6 of the FP64 result everywhere.
+The oracle computes every one of the 10M lookups (FP64 and the FP32 form, on
+the host's cores); the GPU outputs are compared with it element by element:
+the plain FP64 lookup and the benchmark's tuned path (unionized grid indexed
+by material, banded sort, LDS staging in each stage shape at 128 and 256
+lanes) over the whole batch, and the brackets of every (lookup, nuclide)
+pair of the batch for all three grid methods, in 1M-lookup chunks.  Other
+launch shapes are checked through properties that hold at any size: every
+grid method, sort policy and launch shape gives bit-identical sums within
+one precision.
 """
+import os
 import sys
 
 import numpy as np
@@ -21,6 +27,7 @@ from paper_2402_09222_amd import xs  # noqa: E402
 
 N = 10_000_000
 SAMPLES = 20_000
+CHUNK = 1_000_000
 
 
 def say(*a):
@@ -28,22 +35,35 @@ def say(*a):
     sys.stdout.flush()
 
 
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 @pytest.fixture(scope="module")
 def full():
     say("full size: generating tables and 10M queries")
     t = synth.config2_tables()
     q = synth.config2_queries(N)
-    flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED
-    say("full size: building tables (hash 8192 bins, unionized grid)")
+    # the benchmark's build: the union index stored per material
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    say("full size: building tables (hash 8192 bins, union grid by material)")
     h = xs.xs_create_tables(t, flags, 8192)
     E = torch.from_numpy(q.E).to("cuda:0")
     m = torch.from_numpy(q.mat).to("cuda:0")
     s = synth.Stream(41, 1)
     pick = np.unique(np.concatenate([
         s.integers(SAMPLES, 0, N - 1), np.arange(64), np.arange(N - 64, N)]))
-    ref = oracle.lookup(t, q.E[pick], q.mat[pick], threads=8)
-    ref32 = oracle.lookup_f32(t, q.E[pick], q.mat[pick], threads=8)
-    yield dict(t=t, q=q, h=h, E=E, m=m, pick=pick, ref=ref, ref32=ref32)
+    th = host_threads()
+    say(f"full size: oracle over all {N} lookups on {th} threads")
+    ref_all = oracle.lookup(t, q.E, q.mat, threads=th)
+    ref32_all = oracle.lookup_f32(t, q.E, q.mat, threads=th)
+    yield dict(t=t, q=q, h=h, E=E, m=m, pick=pick, ref=ref_all[pick],
+               ref32=ref32_all[pick], ref_all=ref_all, ref32_all=ref32_all)
     h.close()
 
 
@@ -58,14 +78,41 @@ PLAIN = dict(precision=xs.XS_FP64, grid="nuclide", sort="none", block_size=256,
              lookups_per_thread=1)
 
 
-def test_plain_fp64_samples(full):
-    say("plain fp64 full size")
+def test_plain_fp64_whole_batch(full):
+    say("plain fp64 full size, every lookup against the oracle")
     out = run(full, **PLAIN).cpu().numpy()
-    got = out[full["pick"]]
-    assert (np.abs(got - full["ref"]) / full["ref"]).max() <= 1e-12
-    assert np.array_equal(got, full["ref"])
+    ref = full["ref_all"]
+    rel = np.abs(out - ref) / ref
+    say("plain fp64 max rel per channel", rel.max(axis=0))
+    assert rel.max() <= 1e-12
+    assert np.array_equal(out, ref)
     assert np.all(np.isfinite(out)) and np.all(out > 0)
     full["out64"] = torch.from_numpy(out)
+
+
+# Every shape the tuner returns at 10M lookups on these tables: union grid
+# (by material), banded sort, LDS staging in each stage shape, 128- and
+# 256-lane blocks, one or two lookups per lane.
+BENCH_SHAPES = [dict(lds_stage=s, block_size=b, lookups_per_thread=l)
+                for s in (1, 2, 3) for b in (128, 256) for l in (1, 2)]
+
+
+@pytest.mark.parametrize("shape", BENCH_SHAPES,
+                         ids=[f"stage{k['lds_stage']}-b{k['block_size']}-"
+                              f"lpt{k['lookups_per_thread']}"
+                              for k in BENCH_SHAPES])
+def test_tuned_path_whole_batch(full, shape):
+    say("tuned path, every lookup against the oracle", shape)
+    out = run(full, precision=xs.XS_FP32, grid="unionized",
+              sort="band_material", sort_threshold=0, unroll=1,
+              **shape).cpu().numpy()
+    bad = np.count_nonzero(out.view(np.uint32) !=
+                           full["ref32_all"].view(np.uint32))
+    assert bad == 0, (shape, bad)
+    ref = full["ref_all"]
+    rel = np.abs(out.astype(np.float64) - ref) / ref
+    say("  max rel per channel", rel.max(axis=0), "mean", rel.mean(axis=0))
+    assert rel.max() <= 2e-6
 
 
 @pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
@@ -86,7 +133,7 @@ def test_fp32_samples_and_bound(full, grid):
     out = run(full, precision=xs.XS_FP32, grid=grid, sort="material_energy",
               sort_threshold=20000, block_size=256, lookups_per_thread=2)
     o = out.cpu().numpy()
-    assert np.array_equal(o[full["pick"]], full["ref32"])
+    assert np.array_equal(o, full["ref32_all"])
     if "out64" in full:
         ref = full["out64"].numpy()
         rel = np.abs(o.astype(np.float64) - ref) / ref
@@ -141,13 +188,14 @@ def test_sparser_prefixes_in_every_kernel(full, n):
     assert np.array_equal(o.cpu().numpy(), ref)
 
 
-def test_union_by_material_full(full):
-    """Material-major union index (12.6 GB here): identical bits."""
+def test_union_index_by_nuclide_full(full):
+    """The [U][K] union index (5.7 GB here) instead of the per-material one:
+    identical bits."""
     if "out64" not in full:
         pytest.skip("plain run failed")
-    say("union by material, full size")
-    h = xs.xs_create_tables(full["t"], xs.XS_BUILD_FP32 | xs.XS_BUILD_UNIONIZED |
-                            xs.XS_BUILD_UNION_BY_MATERIAL, 0)
+    say("union index [U][K], full size")
+    h = xs.xs_create_tables(full["t"], xs.XS_BUILD_FP32 | xs.XS_BUILD_UNIONIZED,
+                            0)
     try:
         for k in (dict(sort="band_material", sort_threshold=0, lookups_per_thread=1,
                        unroll=4),
@@ -175,22 +223,23 @@ def test_ragged_batch(full):
         assert torch.equal(out.cpu(), full["out64"][:n])
 
 
-@pytest.mark.parametrize("grid", ["hash", "unionized"])
-def test_indices_match_bisection(full, grid):
-    n = 1_000_000
-    say("indices full tables", grid)
+def test_indices_whole_batch(full):
+    """The brackets of every (lookup, nuclide) pair of the 10M batch, from
+    each grid method, against the oracle's, in 1M-lookup chunks."""
     t, q = full["t"], full["q"]
-    off = oracle.index_offsets(t, q.mat[:n])
-    offd = torch.from_numpy(off).to("cuda:0")
-    a = xs.xs_lookup_indices(full["h"], full["E"][:n], full["m"][:n], offd,
-                             grid="nuclide")
-    b = xs.xs_lookup_indices(full["h"], full["E"][:n], full["m"][:n], offd,
-                             grid=grid)
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
-    _, idx_ref, off_s = oracle.lookup(t, q.E[:2000], q.mat[:2000],
-                                      with_index=True)
-    assert np.array_equal(a[:off_s[-1]].cpu().numpy(), idx_ref)
+    th = host_threads()
+    for a in range(0, N, CHUNK):
+        b = min(N, a + CHUNK)
+        say("indices", a, b)
+        _, idx_ref, off = oracle.lookup(t, q.E[a:b], q.mat[a:b],
+                                        with_index=True, threads=th)
+        offd = torch.from_numpy(off).to("cuda:0")
+        for grid in ("nuclide", "hash", "unionized"):
+            got = xs.xs_lookup_indices(full["h"], full["E"][a:b],
+                                       full["m"][a:b], offd, grid=grid)
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), idx_ref), (a, grid)
+            del got
 
 
 @pytest.mark.parametrize("grid,prec", [("unionized", xs.XS_FP64),
