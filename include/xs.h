@@ -242,6 +242,33 @@ xs_status xs_lookup_batch(xs_tables_t tables, int64_t n, const double* d_E,
                           const xs_params* params, void* d_ws, size_t ws_bytes,
                           void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * lookup, parameters, results and errors as xs_lookup_batch, but the sort's
+ * scratch comes from a fixed array inside the library instead of a caller
+ * workspace, so the call allocates nothing (no hipMalloc, no event; calls
+ * are not recorded by xs_profile_begin).  The caller still passes the
+ * queries and the output.
+ *  - Every GPU the library runs on holds one such array of
+ *    XS_NOALLOC_SCRATCH_BYTES (128 MiB) from the library's load until the
+ *    process ends; its address is found once per device by
+ *    xs_create_tables.
+ *  - A sorted batch (sort != XS_SORT_NONE and n >= sort_threshold) may hold
+ *    at most XS_NOALLOC_MAX_SORTED lookups (8,259,456: the paper's 1e5 to
+ *    8e6 particles in flight fit); larger sorted batches return
+ *    XS_EWORKSPACE before anything is enqueued.  Unsorted batches use no
+ *    scratch and take any n xs_lookup_batch takes.
+ *  - All calls on one GPU share that GPU's array, and it keeps the last
+ *    call's contents: calls that overlap in time on one GPU (other host
+ *    threads, or other streams not ordered after this one) race and may
+ *    return wrong results.  Calls on one stream are ordered and safe. */
+#define XS_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define XS_NOALLOC_MAX_SORTED 8259456
+xs_status xs_lookup_batch_noalloc(xs_tables_t tables, int64_t n,
+                                  const double* d_E, const int32_t* d_mat,
+                                  void* d_out, const xs_params* params,
+                                  void* stream);
+
 /* As xs_lookup_batch for the slots whose d_active[q] != 0 (DEVICE uint8
  * [n]); the outputs of other slots are not written.  params->queue picks
  * compaction of the active slots (queued) or a predicated pass over all

@@ -349,7 +349,7 @@ xs_status debug_check(xs_tables_s* h, int64_t n, const double* E,
 xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
                         const int32_t* mat, const uint8_t* active, bool masked,
                         void* out, const xs_params* params, void* ws,
-                        size_t ws_bytes, void* stream) {
+                        size_t ws_bytes, void* stream, bool no_alloc = false) {
   clear_error();
   if (xs_status st = check_handle(h)) return st;
   if (n < 0) return fail(XS_EINVAL, "n must be >= 0");
@@ -381,7 +381,9 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
   hipStream_t s = (hipStream_t)stream;
 
   ProfCall pc{};
-  const bool prof = h->profiling;
+  // Profiling takes (and may create) HIP events, so calls that must not
+  // allocate are not recorded.
+  const bool prof = h->profiling && !no_alloc;
   if (prof) {
     std::lock_guard<std::mutex> lk(h->mu);
     for (auto& e : pc.ev) {
@@ -420,6 +422,14 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
 }
 
 }  // namespace
+
+xs_status lookup_batch_into(xs_tables_t h, int64_t n, const double* E,
+                            const int32_t* mat, void* out,
+                            const xs_params* params, void* ws, size_t ws_bytes,
+                            void* stream) {
+  return lookup_common(h, n, E, mat, nullptr, false, out, params, ws, ws_bytes,
+                       stream, true);
+}
 
 // Untuned batches smaller than one query per lane of the chip (256 compute
 // units x 1024 lanes) default to one wave per query.
@@ -613,6 +623,10 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
   hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
   if (e != hipSuccess)
     return cleanup(fail(XS_EHIP, "table build failed: %s", hipGetErrorString(e)));
+  // Locate this device's fixed scratch array once (xs_lookup_batch_noalloc);
+  // a failure is reported by that entry point, not here.
+  (void)scratch_setup(h->device);
+  clear_error();
   *out = h;
   return XS_OK;
 }

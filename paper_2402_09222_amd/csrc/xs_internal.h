@@ -157,6 +157,18 @@ void clear_error();
 void untuned_defaults(const xs_tables_s* h, int64_t n, int precision,
                       xs_params* out);
 
+// xs_lookup_batch's pipeline on a caller-chosen workspace, without the
+// profiling events (which may allocate); xs_api.hip.
+xs_status lookup_batch_into(xs_tables_t h, int64_t n, const double* E,
+                            const int32_t* mat, void* out,
+                            const xs_params* params, void* ws, size_t ws_bytes,
+                            void* stream);
+
+// The fixed device-side scratch array of xs_lookup_batch_noalloc
+// (xs_noalloc.hip): finds its address on `device` (which must be current)
+// once per device and caches it.  XS_OK or XS_EHIP.
+xs_status scratch_setup(int device);
+
 // Debug mode (xs_debug.hip): resets the current call's words of `counters`
 // and counts the invalid queries among the first n (active ones only when
 // `active` is not null).

@@ -26,6 +26,8 @@ XS_SORT_BAND_MATERIAL = 4
 XS_QUEUE_COMPACT, XS_QUEUE_PREDICATED = 0, 1
 XS_BUILD_FP32, XS_BUILD_HASH, XS_BUILD_UNIONIZED = 1, 2, 4
 XS_BUILD_UNION_BY_MATERIAL = 8
+XS_NOALLOC_SCRATCH_BYTES = 128 << 20
+XS_NOALLOC_MAX_SORTED = 8259456
 INT64_MAX = (1 << 63) - 1
 
 GRIDS = {"nuclide": XS_GRID_NUCLIDE, "hash": XS_GRID_HASH,
@@ -250,6 +252,8 @@ def load_library(path: str = LIB_PATH):
         "xs_resolve_params": ([vp, i64, P(xs_params), P(xs_params)], i32),
         "xs_workspace_size": ([vp, i64, P(xs_params), P(sz)], i32),
         "xs_lookup_batch": ([vp, i64, vp, vp, vp, P(xs_params), vp, sz, vp], i32),
+        "xs_lookup_batch_noalloc": ([vp, i64, vp, vp, vp, P(xs_params), vp],
+                                    i32),
         "xs_lookup_active": ([vp, i64, vp, vp, vp, vp, P(xs_params), vp, sz, vp],
                              i32),
         "xs_lookup_indices": ([vp, i64, vp, vp, vp, vp, i32, vp], i32),
@@ -466,6 +470,21 @@ def xs_lookup_batch(tables: Tables, E, mat, out=None, params: xs_params = None,
         tables.handle, n, ctypes.c_void_p(E.data_ptr()),
         ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(out.data_ptr()), pp,
         ws, nb, _stream_ptr(stream, E.device)), "xs_lookup_batch")
+    return out
+
+
+def xs_lookup_batch_noalloc(tables: Tables, E, mat, out=None,
+                            params: xs_params = None, stream=None):
+    """xs_lookup_batch with the sort's scratch in the library's fixed device
+    array (no workspace, no allocation inside the call).  Returns out."""
+    _check_queries(E, mat)
+    n = E.numel()
+    out = _out_tensor(n, params, E.device, out)
+    pp = ctypes.byref(params) if params is not None else None
+    _check(load_library().xs_lookup_batch_noalloc(
+        tables.handle, n, ctypes.c_void_p(E.data_ptr()),
+        ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(out.data_ptr()), pp,
+        _stream_ptr(stream, E.device)), "xs_lookup_batch_noalloc")
     return out
 
 
