@@ -295,6 +295,21 @@ def parity_fp32(got, ref32, ref64) -> dict:
             "ok": bool(bad == 0 and max(mx) <= TOL_FP32)}
 
 
+def launch_key(p, n):
+    """What decides the kernels a call with parameters p runs for n lookups:
+    the threshold only says whether the sort runs, the hash-bin count only
+    matters under the hash grid."""
+    sorted_ = p.sort != 0 and n >= p.sort_threshold
+    return (p.grid, p.hash_bins if p.grid == 1 else 0,
+            p.sort if sorted_ else 0, p.block_size, p.lookups_per_thread,
+            p.unroll, p.lds_stage, p.wave_per_lookup)
+
+
+# Hash grids built next to the default one for the particles-in-flight sweep
+# and the tuner study (paper Table 1: 100 to 100k bins, default 4,000).
+EXTRA_HASH_BINS = (4000, 32768)
+
+
 def _pctl(v, q):
     v = sorted(v)
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))] if v else 0.0
@@ -309,7 +324,8 @@ def sweep_in_flight(args, torch, synth, xs):
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
              xs.XS_BUILD_UNION_BY_MATERIAL)
-    h = xs.xs_create_tables(t, flags, args.bins)
+    extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
+    h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
     for i, n in enumerate((100_000, 500_000, 1_000_000, 2_000_000, 4_000_000,
                            8_000_000)):
         q = synth.config4_queries(i, n)
@@ -329,7 +345,8 @@ def sweep_in_flight(args, torch, synth, xs):
 
         cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
                                         max_evals=args.tune_evals, reps=3)
-        r = xs.xs_tune(h, E, m, cfg, workspace=ws)
+        r = xs.xs_tune(h, E, m, cfg, workspace=ws, sizes=[n],
+                       cache_path=args.tune_cache)[0]
         best = r.best
         def graph_rate(p):
             """The same call captured once in a HIP graph and replayed."""
@@ -350,8 +367,12 @@ def sweep_in_flight(args, torch, synth, xs):
         row = {"n": n, "mean_nuclides": nbar, "tuned": best.as_dict(),
                "tuned_lookups_per_s": rate(best),
                "tuned_graph_lookups_per_s": graph_rate(best),
-               "tuner": {"evaluated": r.evaluated, "cut": r.cut,
-                         "best_eval": r.best_eval}}
+               "tuned_hash_bins": best.hash_bins,
+               "tuned_sort_threshold": best.sort_threshold,
+               "tuner": {"evaluated": r.evaluated, "measured": r.measured,
+                         "cut": r.cut, "best_eval": r.best_eval,
+                         "space_size": r.space_size,
+                         "from_cache": r.from_cache}}
         plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
                                block_size=256, lookups_per_thread=1, unroll=1,
                                lds_stage=0, sort_threshold=xs.INT64_MAX)
@@ -362,6 +383,7 @@ def sweep_in_flight(args, torch, synth, xs):
             p.block_size, p.lookups_per_thread = best.block_size, best.lookups_per_thread
             p.unroll, p.lds_stage, p.queue = best.unroll, best.lds_stage, best.queue
             p.wave_per_lookup = best.wave_per_lookup
+            p.hash_bins = best.hash_bins
             p.sort_threshold = 0 if sp else xs.INT64_MAX
             row[f"fp32_sort_{name}_lookups_per_s"] = rate(p)
         print(json.dumps(row), flush=True)
@@ -520,7 +542,9 @@ def tuner_study(args, torch, synth, xs):
     q = synth.config4_queries(5, n) if n <= 8_000_000 else synth.config2_queries(n)
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
              xs.XS_BUILD_UNION_BY_MATERIAL)
-    h = xs.xs_create_tables(t, flags, args.bins)
+    extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
+    bins = [args.bins] + extra
+    h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
     E = torch.from_numpy(q.E).to("cuda:0")
     m = torch.from_numpy(q.mat).to("cuda:0")
     out = torch.empty((n, 5), device="cuda:0", dtype=torch.float32)
@@ -529,12 +553,15 @@ def tuner_study(args, torch, synth, xs):
     st = torch.cuda.current_stream()
     ev = (torch.cuda.Event(enable_timing=True),
           torch.cuda.Event(enable_timing=True))
-    keyf = ("grid", "sort", "block_size", "lookups_per_thread", "unroll",
-            "lds_stage", "wave_per_lookup")
-    table = {}
+    keyf = ("grid", "hash_bins", "sort", "block_size", "lookups_per_thread",
+            "unroll", "lds_stage", "wave_per_lookup")
+    table = {}  # launch key -> best of 3 (configurations that launch the
+                # same kernels at this n are timed once)
 
     def measure(p, cutoff):
-        k = tuple(getattr(p, f) for f in keyf)
+        k = launch_key(p, n)
+        if k in table:
+            return table[k]
         xs.xs_lookup_batch(h, E, m, out=out, params=p, workspace=ws)
         best = float("inf")
         for _ in range(3):
@@ -552,7 +579,7 @@ def tuner_study(args, torch, synth, xs):
     t0 = time.perf_counter()
     ex = xs.xs_tune_search(7, xs.xs_tune_config_default(
         precision=xs.XS_FP32, strategy=xs.XS_TUNE_EXHAUSTIVE,
-        timeout_factor=0.0), measure)
+        timeout_factor=0.0, hash_bins=bins), measure)
     wall = time.perf_counter() - t0
     opt = ex.best_ms
     log(f"exhaustive: {ex.space_size} configurations in {wall:.1f} s, "
@@ -564,7 +591,7 @@ def tuner_study(args, torch, synth, xs):
                        "rows": [list(k) + [v] for k, v in table.items()]}, fh)
 
     def replay(p, cutoff):
-        return table[tuple(getattr(p, f) for f in keyf)]
+        return table[launch_key(p, n)]
 
     evals = args.tune_evals
     forest = []
@@ -577,14 +604,20 @@ def tuner_study(args, torch, synth, xs):
             return v
         r = xs.xs_tune_search(7, xs.xs_tune_config_default(
             precision=xs.XS_FP32, strategy=xs.XS_TUNE_FOREST,
-            max_evals=evals, seed=seed), rec)
+            max_evals=evals, seed=seed, hash_bins=bins), rec)
         run_best = np.minimum.accumulate(trace)
         hit = np.nonzero(run_best <= 1.05 * opt)[0]
         forest.append((r.best_ms / opt, int(hit[0]) + 1 if len(hit) else None))
-    costs = np.array(sorted(table.values()))
+    # every configuration of the space, each at its launch's time
+    allc = []
+    xs.xs_tune_search(7, xs.xs_tune_config_default(
+        precision=xs.XS_FP32, strategy=xs.XS_TUNE_EXHAUSTIVE,
+        timeout_factor=0.0, hash_bins=bins),
+        lambda p, cutoff: allc.append(replay(p, cutoff)) or allc[-1])
+    allv = np.array(allc)
+    costs = np.sort(allv)
     rng = np.random.default_rng(7)
     rand = []
-    allv = np.array(list(table.values()))
     for seed in range(args.study_seeds):
         pick = allv[rng.choice(len(allv), evals, replace=False)]
         run_best = np.minimum.accumulate(pick)
@@ -600,6 +633,7 @@ def tuner_study(args, torch, synth, xs):
                 "median_evals_to_5pct": (float(np.median(hits)) if hits
                                          else None)}
     line = {"study": "tuner", "n_lookups": n, "space_size": ex.space_size,
+            "distinct_launches": len(table), "hash_bins": bins,
             "evals_per_search": evals, "seeds": args.study_seeds,
             "exhaustive": {"best_ms": opt, "best": ex.best.as_dict(),
                            "wall_s": wall,
@@ -798,6 +832,9 @@ def main(argv=None):
                     help="JSON dict of FP32 params instead of tuning")
     ap.add_argument("--tune-evals", type=int, default=96,
                     help="evaluation budget of the forest-surrogate tuner")
+    ap.add_argument("--tune-cache", type=str, default=None,
+                    help="tuned-parameter file read before and written after "
+                    "tuning (--config 4)")
     ap.add_argument("--tune-strategy", choices=["forest", "exhaustive"],
                     default="forest")
     ap.add_argument("--only", choices=["plain", "tuned"], default=None,

@@ -109,8 +109,18 @@ typedef struct xs_tables_s* xs_tables_t;
  *  - mat_nuclides: ids in [0, n_nuclides), no id twice within a material,
  *    any order (the sum follows this list order);
  *  - mat_density: finite and > 0;
+ *  - with XS_BUILD_FP32, every nonzero channel value and every density must
+ *    round to a normal finite FP32 number (about 1.2e-38 to 3.4e38), since
+ *    the FP32 form's relative error bound holds only there;
  *  - n_hash_bins in [1, 100000] when XS_BUILD_HASH is set (the paper's range
- *    is 100 to 100k; 1 bin makes every search a full bisection). */
+ *    is 100 to 100k; 1 bin makes every search a full bisection);
+ *  - with XS_BUILD_HASH, n_extra_hash_grids in [0, XS_MAX_HASH_GRIDS - 1]
+ *    further hash grids of extra_hash_bins[i] bins each, every count in
+ *    [1, 100000] and all counts (n_hash_bins included) distinct; without
+ *    XS_BUILD_HASH it must be 0.  Grid HASH then searches the grid that
+ *    xs_params.hash_bins names (paper Table 1: the bin count is a tunable
+ *    that trades memory for search length); n_hash_bins is the default. */
+#define XS_MAX_HASH_GRIDS 8
 typedef struct {
   int32_t n_nuclides;
   int32_t n_channels;
@@ -122,7 +132,9 @@ typedef struct {
   const int32_t* mat_nuclides; /* [mat_offsets[n_materials]] */
   const double* mat_density;   /* [mat_offsets[n_materials]] */
   uint32_t build_flags;        /* XS_BUILD_* bits */
-  int32_t n_hash_bins;
+  int32_t n_hash_bins;         /* bins of the default hash grid */
+  int32_t n_extra_hash_grids;  /* further hash grids (0 = none) */
+  const int32_t* extra_hash_bins; /* [n_extra_hash_grids] bin counts */
 } xs_table_desc;
 
 /* Launch and method parameters of one lookup call.  Every field except
@@ -163,6 +175,11 @@ typedef struct {
                                  material (small batches); needs
                                  lookups_per_thread = unroll = 1, lds_stage
                                  = 0 and block_size <= 256 */
+  int32_t hash_bins;          /* grid HASH only: bin count of the built hash
+                                 grid to search (XS_ENOTBUILT if none has
+                                 it); 0 or XS_AUTO: the tuned one, else the
+                                 default grid.  Resolves to 0 for the other
+                                 grid methods (a conditional parameter) */
 } xs_params;
 
 /* Sizes of a built handle. */
@@ -173,6 +190,12 @@ typedef struct {
   uint32_t build_flags;
   uint32_t reserved;
   double e_min, e_max;       /* smallest first and largest last grid energy */
+  int32_t n_hash_grids;      /* hash grids built (0 without XS_BUILD_HASH) */
+  int32_t hash_bins[XS_MAX_HASH_GRIDS]; /* their bin counts, default first */
+  int32_t reserved2;
+  uint64_t checksum;         /* 64-bit digest of every array of the table
+                                description, the build flags and the hash-bin
+                                counts: the key of tuned-parameter caches */
   size_t bytes_grid;         /* search grid (FP64 energies) */
   size_t bytes_fp64;         /* FP64 interpolation records */
   size_t bytes_fp32;         /* FP32 interpolation records */
@@ -296,6 +319,19 @@ xs_status xs_lookup_indices(xs_tables_t tables, int64_t n, const double* d_E,
 #define XS_TUNE_EXHAUSTIVE 0
 #define XS_TUNE_FOREST 1
 
+/* The space (paper section 5.2 builds its space the same way, with
+ * conditional parameters):
+ *   grid method (built and in grid_mask)
+ *     hash_bins      one of the hash grids on offer   | grid == HASH
+ *   sort policy (in sort_mask)
+ *     sort_threshold 0 (always sort), 20,000 (the    | sort != NONE
+ *                    paper's default) or INT64_MAX
+ *                    (never), paper Table 1
+ *   queue mode       COMPACT or PREDICATED            | active == 1
+ *   block size 64..1024 x (lookups per lane, nuclides in flight, LDS stage
+ *   shape, wave per lookup), invalid combinations excluded.
+ * An inactive parameter holds a fixed value (hash_bins 0, sort_threshold
+ * INT64_MAX, queue COMPACT) and is never varied. */
 typedef struct {
   int32_t precision;      /* XS_FP64 or XS_FP32 */
   int32_t strategy;       /* XS_TUNE_* */
@@ -308,7 +344,8 @@ typedef struct {
   int32_t reps;           /* timed runs per configuration, best kept (the
                              paper reports the best of 5) */
   int32_t warmup;         /* untimed runs per configuration */
-  int32_t reserved;       /* must be 0 */
+  int32_t active;         /* 0: tune xs_lookup_batch; 1: xs_lookup_active
+                             (the queue mode joins the space) */
   double timeout_factor;  /* a configuration whose first timed run exceeds
                              factor x the baseline's time is stopped and
                              scored at that time-out (paper: 1.5); <= 0
@@ -317,6 +354,10 @@ typedef struct {
   uint64_t seed;          /* random initial samples and bootstrap draws */
   uint32_t grid_mask;     /* bit g: consider grid method g (0 = all built) */
   uint32_t sort_mask;     /* bit s: consider sort policy s (0 = all) */
+  int32_t n_hash_grids;   /* xs_tune_search only: the hash grids on offer
+                             (0: one grid, hash_bins 0); xs_tune offers
+                             every hash grid of the handle */
+  int32_t hash_bins[XS_MAX_HASH_GRIDS];
 } xs_tune_config;
 
 typedef struct {
@@ -324,10 +365,17 @@ typedef struct {
   double best_ms;
   xs_params baseline;     /* the library default, evaluated first */
   double baseline_ms;
-  int32_t evaluated;      /* configurations run, baseline included */
+  int32_t evaluated;      /* configurations run, baseline included (0 when
+                             the entry came from a cache) */
   int32_t cut;            /* of which stopped at the time-out */
   int32_t space_size;     /* valid configurations in the space */
   int32_t best_eval;      /* 1-based evaluation at which `best` was found */
+  int64_t n;              /* xs_tune: the batch size tuned */
+  int32_t from_cache;     /* xs_tune: 1 if read from the cache file */
+  int32_t measured;       /* xs_tune: evaluations that ran on the device (a
+                             configuration that launches the same kernels
+                             at this n as one already timed reuses its
+                             time) */
 } xs_tune_result;
 
 /* Evaluator used by xs_tune_search: run configuration *p and store its time
@@ -339,33 +387,91 @@ typedef xs_status (*xs_eval_fn)(const xs_params* p, double cutoff_ms,
 
 /* Fills *c with the defaults: FOREST, 48 evaluations, 10 initial samples,
  * batch 1, best of 5 after 1 warm-up, time-out 1.5x baseline, kappa 1.96,
- * seed 1234, all grids and sorts. */
+ * seed 1234, all grids and sorts, xs_lookup_batch. */
 xs_status xs_tune_config_default(xs_tune_config* c);
 
-/* Searches the space of (grid method in built_grids & grid_mask) x (sort
- * policy) x (block size 64..1024) x (lookups per lane, nuclides in flight,
- * LDS stage shape, wave per lookup), invalid combinations excluded, calling
- * `eval` for each configuration it picks; the first is the baseline (hash
- * grid if built, banded sort, block 256, two nuclides in flight).  No
- * device call of its own. */
+/* Searches the space above over the grid methods in built_grids & grid_mask
+ * and the hash grids cfg lists, calling `eval` for each configuration it
+ * picks; the first is the baseline (hash grid if built, banded sort at
+ * threshold 20,000, block 256, two nuclides in flight).  No device call of
+ * its own. */
 xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
                          xs_eval_fn eval, void* user, xs_tune_result* result);
 
-/* Tunes xs_lookup_batch for batches of n lookups on the caller's sample
- * (DEVICE d_E / d_mat [n], d_out [n][5] of the precision's type, d_ws at
- * least xs_workspace_size(n) with a sort), timing each configuration with
- * HIP events on `stream`; the baseline is the untuned default for n, so the
- * result is never slower than it.  Records the winner in the handle for the
+/* A tuning request (paper section 3: ytopt proposes configurations, workers
+ * run them and the results go to a performance database).  All pointers
+ * DEVICE unless marked HOST. */
+typedef struct {
+  int32_t n_sizes;            /* batch sizes to tune, 1..64 */
+  int32_t reserved;           /* must be 0 */
+  const int64_t* sizes;       /* HOST [n_sizes], each in [1, 2^31 - 1]; e.g.
+                                 the paper's particles in flight 1e5..8e6 */
+  const double* d_E;          /* sample queries [max size]; size n tunes on
+                                 the first n */
+  const int32_t* d_mat;       /* [max size] */
+  const uint8_t* d_active;    /* [max size] with config.active, else NULL */
+  void* d_out;                /* [max size][5] of the precision's type */
+  void* d_ws;                 /* 256-byte aligned, at least
+                                 xs_workspace_size(max size) with a sort */
+  size_t ws_bytes;
+  void* stream;
+  const char* cache_path;     /* HOST file of tuned parameters, or NULL */
+  xs_tune_config config;
+} xs_tune_request;
+
+/* Tunes every size of the request (xs_lookup_batch, or xs_lookup_active
+ * with config.active) and records each winner in the handle for the
  * batch-size class floor(log2 n): later calls whose fields are XS_AUTO use
- * the tuned value of the nearest class.  Synchronises `stream`. */
-xs_status xs_tune(xs_tables_t tables, int64_t n, const double* d_E,
-                  const int32_t* d_mat, void* d_out, void* d_ws,
-                  size_t ws_bytes, void* stream, const xs_tune_config* cfg,
-                  xs_tune_result* result);
+ * the tuned value of the nearest class of the same entry point.  Each size's
+ * baseline is the untuned default for it, so a result is never slower than
+ * what an untuned call would run.  With a cache path, a size whose key
+ * (device, table checksum, precision, entry point, class) the file holds is
+ * taken from it without running anything, and each newly tuned size is
+ * written to it (the file is rewritten through a temporary file and a
+ * rename, so a reader never sees half a file).  results[n_sizes] (HOST)
+ * receives one entry per size, in order.  Synchronises the stream.
+ * Errors: XS_EINVAL (sizes, pointers, config), XS_EWORKSPACE, XS_ENOTBUILT,
+ * XS_EHIP; a cache file that cannot be written is XS_EINVAL after the
+ * results are recorded in the handle. */
+xs_status xs_tune(xs_tables_t tables, const xs_tune_request* req,
+                  xs_tune_result* results);
 
 /* Records complete parameters (no XS_AUTO field) as tuned for the class of
- * n, e.g. restored from a cache file; p == NULL clears every tuned entry. */
-xs_status xs_set_tuned(xs_tables_t tables, int64_t n, const xs_params* p);
+ * n, for xs_lookup_batch (active 0) or xs_lookup_active (active 1); p ==
+ * NULL clears every tuned entry of both. */
+xs_status xs_set_tuned(xs_tables_t tables, int64_t n, int32_t active,
+                       const xs_params* p);
+
+/* Loads every entry of a tuned-parameter file whose device and table
+ * checksum match this handle and device into the handle (as xs_set_tuned
+ * would); entries that no longer resolve (a grid not built) are skipped.
+ * *loaded (may be NULL) gets the number loaded.  A missing file loads 0. */
+xs_status xs_tune_load(xs_tables_t tables, const char* cache_path,
+                       int32_t* loaded);
+
+/* The key of a tuned-parameter entry. */
+typedef struct {
+  char device[96];        /* device name, architecture and compute units */
+  uint64_t checksum;      /* xs_table_info_t.checksum */
+  int32_t precision;
+  int32_t active;         /* 0 xs_lookup_batch, 1 xs_lookup_active */
+  int32_t size_class;     /* floor(log2 n) */
+  int32_t reserved;
+} xs_tune_key;
+
+/* The file format, for tools that read or fill a cache without a device:
+ * xs_tune_cache_get finds the entry of *key in the file (XS_OK, *p and
+ * *best_ms filled; XS_ENOTBUILT if the file has no such entry or does not
+ * exist); xs_tune_cache_put adds or replaces it (atomic rewrite). */
+xs_status xs_tune_cache_get(const char* cache_path, const xs_tune_key* key,
+                            xs_params* p, double* best_ms);
+xs_status xs_tune_cache_put(const char* cache_path, const xs_tune_key* key,
+                            const xs_params* p, double best_ms);
+
+/* The key of this handle, on the current device, for (precision, active,
+ * n). */
+xs_status xs_tune_key_of(xs_tables_t tables, int32_t precision,
+                         int32_t active, int64_t n, xs_tune_key* key);
 
 /* ---- request streams ------------------------------------------------------ */
 

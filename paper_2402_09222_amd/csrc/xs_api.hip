@@ -2,6 +2,7 @@
 // upload, parameter resolution, the lookup pipeline (optional sort or
 // compaction, then the lookup kernel) and per-stage event timing.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -38,6 +39,58 @@ int64_t double_bits(double x) {
   int64_t b;
   std::memcpy(&b, &x, sizeof(b));
   return b;
+}
+
+// 64-bit digest of a table description: every array, the build flags and
+// the hash-bin counts, in 8-byte words (a multiply-rotate mix per word, then
+// a final avalanche; Stafford's variant 13 of the MurmurHash3 finaliser).
+struct Digest {
+  uint64_t h = 0x243F6A8885A308D3ull;
+  void word(uint64_t w) {
+    h ^= w * 0x9E3779B97F4A7C15ull;
+    h = (h << 27 | h >> 37) * 0xC2B2AE3D27D4EB4Full + 0x165667B19E3779F9ull;
+  }
+  void bytes(const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, c + i, 8);
+      word(w);
+    }
+    uint64_t w = 0;
+    std::memcpy(&w, c + i, n - i);
+    word(w ^ ((uint64_t)(n - i) << 56));
+    word(n);
+  }
+  uint64_t done() const {
+    uint64_t z = h;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+uint64_t table_checksum(const xs_table_desc* d) {
+  Digest g;
+  const int K = d->n_nuclides, M = d->n_materials;
+  const int64_t P = d->grid_offsets[K];
+  const int32_t L = d->mat_offsets[M];
+  g.word((uint64_t)K);
+  g.word((uint64_t)M);
+  g.bytes(d->grid_offsets, sizeof(int64_t) * (K + 1));
+  g.bytes(d->energy, sizeof(double) * P);
+  g.bytes(d->xs, sizeof(double) * P * XS_CHANNELS);
+  g.bytes(d->mat_offsets, sizeof(int32_t) * (M + 1));
+  g.bytes(d->mat_nuclides, sizeof(int32_t) * L);
+  g.bytes(d->mat_density, sizeof(double) * L);
+  g.word(d->build_flags);
+  if (d->build_flags & XS_BUILD_HASH) {
+    g.word((uint64_t)d->n_hash_bins);
+    for (int i = 0; i < d->n_extra_hash_grids; ++i)
+      g.word((uint64_t)d->extra_hash_bins[i]);
+  }
+  return g.done();
 }
 
 // Frees what a partially built handle holds.
@@ -85,6 +138,15 @@ xs_status alloc_dev(xs_tables_s* h, size_t bytes, void** dst) {
   return XS_OK;
 }
 
+// The FP32 form keeps a relative error bound only while every channel value
+// and density is zero or rounds to a normal, finite FP32 number: larger ones
+// would become infinite, smaller ones subnormal or zero.
+bool fp32_normal_or_zero(double x) {
+  if (x == 0.0) return true;
+  const float f = (float)x;
+  return std::isfinite(f) && std::fabs(f) >= FLT_MIN;
+}
+
 // Host-only checks of a table description (no HIP call).
 xs_status validate_desc(const xs_table_desc* d) {
   if (!d) return fail(XS_EINVAL, "desc is NULL");
@@ -106,8 +168,30 @@ xs_status validate_desc(const xs_table_desc* d) {
   if ((d->build_flags & XS_BUILD_HASH) &&
       (d->n_hash_bins < 1 || d->n_hash_bins > 100000))
     return fail(XS_EINVAL, "n_hash_bins must be in [1, 100000]");
+  if (d->n_extra_hash_grids != 0) {
+    if (!(d->build_flags & XS_BUILD_HASH))
+      return fail(XS_EINVAL, "extra hash grids need XS_BUILD_HASH");
+    if (d->n_extra_hash_grids < 0 ||
+        d->n_extra_hash_grids > XS_MAX_HASH_GRIDS - 1)
+      return fail(XS_EINVAL, "n_extra_hash_grids must be in [0, %d]",
+                  XS_MAX_HASH_GRIDS - 1);
+    if (!d->extra_hash_bins)
+      return fail(XS_EINVAL, "extra_hash_bins is NULL");
+    for (int i = 0; i < d->n_extra_hash_grids; ++i) {
+      const int32_t b = d->extra_hash_bins[i];
+      if (b < 1 || b > 100000)
+        return fail(XS_EINVAL, "extra_hash_bins[%d] = %d not in [1, 100000]",
+                    i, b);
+      if (b == d->n_hash_bins)
+        return fail(XS_EINVAL, "extra_hash_bins[%d] repeats n_hash_bins", i);
+      for (int j = 0; j < i; ++j)
+        if (d->extra_hash_bins[j] == b)
+          return fail(XS_EINVAL, "extra_hash_bins lists %d twice", b);
+    }
+  }
 
   const int K = d->n_nuclides;
+  const bool fp32 = (d->build_flags & XS_BUILD_FP32) != 0;
   if (d->grid_offsets[0] != 0) return fail(XS_ETABLE, "grid_offsets[0] != 0");
   for (int k = 0; k < K; ++k) {
     const int64_t a = d->grid_offsets[k], b = d->grid_offsets[k + 1];
@@ -131,6 +215,10 @@ xs_status validate_desc(const xs_table_desc* d) {
         if (!std::isfinite(x) || x < 0.0)
           return fail(XS_ETABLE, "nuclide %d point %lld channel %d: value %g "
                       "not finite and >= 0", k, (long long)(p - a), c, x);
+        if (fp32 && !fp32_normal_or_zero(x))
+          return fail(XS_ETABLE, "nuclide %d point %lld channel %d: value %g "
+                      "does not round to a normal FP32 number or zero "
+                      "(XS_BUILD_FP32)", k, (long long)(p - a), c, x);
       }
     }
   }
@@ -151,6 +239,9 @@ xs_status validate_desc(const xs_table_desc* d) {
       if (!std::isfinite(r) || !(r > 0.0))
         return fail(XS_ETABLE, "material %d: density %g not finite and > 0", m,
                     r);
+      if (fp32 && !fp32_normal_or_zero(r))
+        return fail(XS_ETABLE, "material %d: density %g does not round to a "
+                    "normal FP32 number (XS_BUILD_FP32)", m, r);
     }
   }
   return XS_OK;
@@ -161,22 +252,29 @@ xs_status check_handle(xs_tables_t h) {
   return XS_OK;
 }
 
-const xs_params* nearest_tuned(const xs_tables_s* h, int prec, int64_t n) {
-  const int want = n > 0 ? 63 - __builtin_clzll((unsigned long long)n) : 0;
+const xs_params* nearest_tuned(const xs_tables_s* h, int active, int prec,
+                               int64_t n) {
+  const int want = size_class(n);
   int best = -1, dist = 1 << 30;
   for (int b = 0; b < kBuckets; ++b) {
-    if (!h->tuned_valid[prec][b]) continue;
+    if (!h->tuned_valid[active][prec][b]) continue;
     const int dd = std::abs(b - want);
     if (dd < dist) {
       dist = dd;
       best = b;
     }
   }
-  return best < 0 ? nullptr : &h->tuned[prec][best];
+  return best < 0 ? nullptr : &h->tuned[active][prec][best];
+}
+
+bool hash_built(const xs_tables_s* h, int32_t bins) {
+  for (const HashGrid& g : h->hash)
+    if (g.B == bins) return true;
+  return false;
 }
 
 xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
-                  xs_params* out) {
+                  xs_params* out, int active = 0) {
   xs_params p;
   if (in) {
     p = *in;
@@ -192,7 +290,7 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   bool have_tuned = false;
   {
     std::lock_guard<std::mutex> lk(h->mu);
-    const xs_params* tp = nearest_tuned(h, p.precision, n);
+    const xs_params* tp = nearest_tuned(h, active, p.precision, n);
     if (tp) {
       t = *tp;
       have_tuned = true;
@@ -226,6 +324,19 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.grid < 0 || p.grid > 2) return fail(XS_EINVAL, "unknown grid %d", p.grid);
   if (p.grid == XS_GRID_HASH && h->d.B == 0)
     return fail(XS_ENOTBUILT, "hash grid was not built (XS_BUILD_HASH)");
+  // hash_bins is conditional on the hash grid: automatic means the tuned
+  // grid when the tuned entry searches a hash grid that was built, else the
+  // default one; other grid methods carry 0.
+  if (p.grid != XS_GRID_HASH) {
+    p.hash_bins = 0;
+  } else {
+    if (p.hash_bins == 0 || p.hash_bins == XS_AUTO)
+      p.hash_bins = (t.grid == XS_GRID_HASH && hash_built(h, t.hash_bins))
+                        ? t.hash_bins : h->d.B;
+    if (!hash_built(h, p.hash_bins))
+      return fail(XS_ENOTBUILT, "no hash grid of %d bins was built",
+                  p.hash_bins);
+  }
   if (p.grid == XS_GRID_UNIONIZED && h->d.U == 0)
     return fail(XS_ENOTBUILT, "unionized grid was not built (XS_BUILD_UNIONIZED)");
   if (p.sort < 0 || p.sort > 4) return fail(XS_EINVAL, "unknown sort %d", p.sort);
@@ -355,7 +466,7 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
   if (n < 0) return fail(XS_EINVAL, "n must be >= 0");
   if (n > 0x7fffffffLL) return fail(XS_EINVAL, "n must be < 2^31");
   xs_params p;
-  if (xs_status st = resolve(h, n, params, &p)) return st;
+  if (xs_status st = resolve(h, n, params, &p, masked ? 1 : 0)) return st;
   if (n == 0) return XS_OK;
   if (!E || !mat || !out) return fail(XS_EINVAL, "query or output pointer is NULL");
   if (masked && !active) return fail(XS_EINVAL, "active mask is NULL");
@@ -404,10 +515,11 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
   }
   if (prof) XS_HIP(hipEventRecord(pc.ev[1], s));
   hipError_t e;
+  const DevTables d = tables_for(h, p);
   switch (p.grid) {
-    case XS_GRID_NUCLIDE: e = launch_lookup_nuclide(h->d, p, a, s); break;
-    case XS_GRID_HASH: e = launch_lookup_hash(h->d, p, a, s); break;
-    default: e = launch_lookup_union(h->d, p, a, s); break;
+    case XS_GRID_NUCLIDE: e = launch_lookup_nuclide(d, p, a, s); break;
+    case XS_GRID_HASH: e = launch_lookup_hash(d, p, a, s); break;
+    default: e = launch_lookup_union(d, p, a, s); break;
   }
   if (e != hipSuccess)
     return fail(XS_EHIP, "lookup kernel launch failed: %s", hipGetErrorString(e));
@@ -422,6 +534,27 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
 }
 
 }  // namespace
+
+int size_class(int64_t n) {
+  return n > 1 ? 63 - __builtin_clzll((unsigned long long)n) : 0;
+}
+
+xs_status resolve_for(xs_tables_s* h, int64_t n, int active,
+                      const xs_params* in, xs_params* out) {
+  return resolve(h, n, in, out, active);
+}
+
+DevTables tables_for(const xs_tables_s* h, const xs_params& p) {
+  DevTables d = h->d;
+  if (p.grid == XS_GRID_HASH)
+    for (const HashGrid& g : h->hash)
+      if (g.B == p.hash_bins) {
+        d.B = g.B;
+        d.inv_dln = g.inv_dln;
+        d.H = g.H;
+      }
+  return d;
+}
 
 xs_status lookup_batch_into(xs_tables_t h, int64_t n, const double* E,
                             const int32_t* mat, void* out,
@@ -448,10 +581,12 @@ void untuned_defaults(const xs_tables_s* h, int64_t n, int precision,
   t.queue = XS_QUEUE_COMPACT;
   t.unroll = 2;
   t.wave_per_lookup = 0;
+  t.hash_bins = t.grid == XS_GRID_HASH ? h->d.B : 0;
   if (n < kWaveDefaultBelow) {
     // Too few queries to give every lane of the chip one: a wave per
     // query, unsorted, on the fastest grid that was built.
     t.grid = h->d.U > 0 ? XS_GRID_UNIONIZED : t.grid;
+    t.hash_bins = t.grid == XS_GRID_HASH ? h->d.B : 0;
     t.sort = XS_SORT_NONE;
     t.block_size = 128;
     t.unroll = 1;
@@ -560,22 +695,34 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
   info.bytes_materials = (size_t)(M + 1) * 4 + (size_t)L * (sizeof(MatRec) + 8);
 
   if (desc->build_flags & XS_BUILD_HASH) {
-    const int B = desc->n_hash_bins;
-    d.B = B;
+    // The default grid first, then the extra ones; every grid spans the same
+    // [e_min, e_max] in ln E.
     d.ln_emin = std::log(e_min);
     const double span = std::log(e_max) - d.ln_emin;
-    d.inv_dln = (double)B / span;
-    void* H;
-    const size_t bytes = (size_t)(B + 1) * K * 4;
-    if ((st = alloc_dev(h, bytes, &H))) return cleanup(st);
-    d.H = (const int32_t*)H;
-    hipError_t e = launch_hash_build(d, goff_dev, span / B, (int32_t*)H, s);
-    if (e != hipSuccess)
-      return cleanup(fail(XS_EHIP, "hash build launch failed: %s",
-                          hipGetErrorString(e)));
-    info.n_hash_bins = B;
-    info.bytes_hash = bytes;
+    for (int g = 0; g <= desc->n_extra_hash_grids; ++g) {
+      const int B = g == 0 ? desc->n_hash_bins : desc->extra_hash_bins[g - 1];
+      void* H;
+      const size_t bytes = (size_t)(B + 1) * K * 4;
+      if ((st = alloc_dev(h, bytes, &H))) return cleanup(st);
+      DevTables db = d;
+      db.B = B;
+      db.inv_dln = (double)B / span;
+      db.H = (const int32_t*)H;
+      hipError_t e = launch_hash_build(db, goff_dev, span / B, (int32_t*)H, s);
+      if (e != hipSuccess)
+        return cleanup(fail(XS_EHIP, "hash build launch failed: %s",
+                            hipGetErrorString(e)));
+      h->hash.push_back(HashGrid{B, db.inv_dln, db.H});
+      info.hash_bins[g] = B;
+      info.bytes_hash += bytes;
+    }
+    d.B = h->hash[0].B;
+    d.inv_dln = h->hash[0].inv_dln;
+    d.H = h->hash[0].H;
+    info.n_hash_bins = d.B;
+    info.n_hash_grids = (int32_t)h->hash.size();
   }
+  info.checksum = table_checksum(desc);
   if (desc->build_flags & XS_BUILD_UNIONIZED) {
     std::vector<double> u(desc->energy, desc->energy + P);
     std::sort(u.begin(), u.end());
@@ -662,6 +809,7 @@ xs_status xs_params_default(xs_params* p, int32_t precision) {
   p->sort_threshold = -1;
   p->queue = XS_AUTO;
   p->unroll = 0;
+  p->hash_bins = XS_AUTO;
   return XS_OK;
 }
 
@@ -680,16 +828,19 @@ xs_status xs_workspace_size(xs_tables_t h, int64_t n, const xs_params* params,
   if (xs_status st = check_handle(h)) return st;
   if (!bytes) return fail(XS_EINVAL, "bytes is NULL");
   if (n < 0 || n > 0x7fffffffLL) return fail(XS_EINVAL, "n out of range");
-  xs_params p;
-  if (xs_status st = resolve(h, n, params, &p)) return st;
   size_t b = 0;
-  if (n > 0) {
-    // Enough for either entry point: a sort (with or without the active
-    // flag) or a compaction.
-    if (p.sort != XS_SORT_NONE && n >= p.sort_threshold)
-      b = sort_workspace_bytes(n, 32);
-    else
-      b = compact_workspace_bytes(n);
+  // Enough for either entry point, each resolving automatic fields from its
+  // own tuned entries: a sort (with or without the active flag) or a
+  // compaction.
+  for (int active = 0; active < 2; ++active) {
+    xs_params p;
+    if (xs_status st = resolve(h, n, params, &p, active)) return st;
+    if (n > 0) {
+      if (p.sort != XS_SORT_NONE && n >= p.sort_threshold)
+        b = std::max(b, sort_workspace_bytes(n, 32));
+      else
+        b = std::max(b, compact_workspace_bytes(n));
+    }
   }
   *bytes = b;
   return XS_OK;

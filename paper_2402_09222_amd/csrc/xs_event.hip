@@ -174,7 +174,8 @@ xs_status xs_event_run(xs_tables_t h, const xs_event_config* cfg,
                        (!b->t_collisions || !b->t_energy || !b->t_fate)))
     return fail(XS_EINVAL, "a buffer is NULL");
   xs_params p;
-  if (xs_status st = xs_resolve_params(h, cfg->n_slots, params, &p)) return st;
+  // resolved as xs_lookup_active (which runs the lookups) resolves them
+  if (xs_status st = resolve_for(h, cfg->n_slots, 1, params, &p)) return st;
   hipStream_t s = (hipStream_t)stream;
 
   EventDev d{};

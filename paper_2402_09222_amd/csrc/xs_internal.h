@@ -109,6 +109,13 @@ constexpr int kRadixBins = 1 << kRadixBits;
 
 constexpr int kBuckets = 48;  // tuned parameters per floor(log2(n))
 
+// One logarithmic hash grid of a handle (the default first).
+struct HashGrid {
+  int32_t B;
+  double inv_dln;
+  const int32_t* H;
+};
+
 struct ProfCall {
   hipEvent_t ev[3];  // before sort, after sort, after lookup
   bool sorted;
@@ -122,8 +129,12 @@ struct xs_tables_s {
   xs::DevTables d{};
   xs_table_info_t info{};
   std::vector<void*> allocations;
-  bool tuned_valid[2][xs::kBuckets] = {};
-  xs_params tuned[2][xs::kBuckets] = {};
+  // every hash grid built (d's B, inv_dln and H are those of the first)
+  std::vector<xs::HashGrid> hash;
+  // tuned parameters per entry point (0 xs_lookup_batch, 1
+  // xs_lookup_active), precision and batch-size class
+  bool tuned_valid[2][2][xs::kBuckets] = {};
+  xs_params tuned[2][2][xs::kBuckets] = {};
   std::mutex mu;
   bool profiling = false;
   std::vector<xs::ProfCall> prof;
@@ -156,6 +167,18 @@ void clear_error();
 // (every field set; xs_api.hip).
 void untuned_defaults(const xs_tables_s* h, int64_t n, int precision,
                       xs_params* out);
+
+// Resolves automatic fields for entry point `active` (0 xs_lookup_batch, 1
+// xs_lookup_active) and checks the result; xs_api.hip.
+xs_status resolve_for(xs_tables_s* h, int64_t n, int active,
+                      const xs_params* in, xs_params* out);
+
+// The device tables a call with resolved parameters p runs on: the handle's,
+// with the hash grid p.hash_bins names when p.grid is HASH.
+DevTables tables_for(const xs_tables_s* h, const xs_params& p);
+
+// Batch-size class of n: floor(log2 n), 0 for n <= 1.
+int size_class(int64_t n);
 
 // xs_lookup_batch's pipeline on a caller-chosen workspace, without the
 // profiling events (which may allocate); xs_api.hip.

@@ -448,13 +448,13 @@ xs_status xs_lookup_requests(xs_tables_t h, const xs_request* reqs,
   hipError_t e;
   switch (p.grid) {
     case XS_GRID_NUCLIDE:
-      e = launch_requests_p<XS_GRID_NUCLIDE>(p, h->d, reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
+      e = launch_requests_p<XS_GRID_NUCLIDE>(p, tables_for(h, p), reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
       break;
     case XS_GRID_HASH:
-      e = launch_requests_p<XS_GRID_HASH>(p, h->d, reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
+      e = launch_requests_p<XS_GRID_HASH>(p, tables_for(h, p), reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
       break;
     default:
-      e = launch_requests_p<XS_GRID_UNIONIZED>(p, h->d, reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
+      e = launch_requests_p<XS_GRID_UNIONIZED>(p, tables_for(h, p), reqs_dev, count, stamps, plan.tiles, bmin, shift, s);
       break;
   }
   if (e != hipSuccess)
@@ -662,7 +662,7 @@ xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
 
   // Kernel arguments live in the handle; the nodes point at them.  Until the
   // first submit the run node has no tiles and matches no descriptor.
-  s->a_t = h->d;
+  s->a_t = tables_for(h, p);
   s->a_reqs = s->reqs_dev;
   s->a_stamps = s->stamps_dev;
   s->a_count = 1;

@@ -26,6 +26,7 @@ XS_SORT_BAND_MATERIAL = 4
 XS_QUEUE_COMPACT, XS_QUEUE_PREDICATED = 0, 1
 XS_BUILD_FP32, XS_BUILD_HASH, XS_BUILD_UNIONIZED = 1, 2, 4
 XS_BUILD_UNION_BY_MATERIAL = 8
+XS_MAX_HASH_GRIDS = 8
 XS_NOALLOC_SCRATCH_BYTES = 128 << 20
 XS_NOALLOC_MAX_SORTED = 8259456
 INT64_MAX = (1 << 63) - 1
@@ -56,6 +57,8 @@ class xs_table_desc(ctypes.Structure):
         ("mat_density", ctypes.c_void_p),
         ("build_flags", ctypes.c_uint32),
         ("n_hash_bins", ctypes.c_int32),
+        ("n_extra_hash_grids", ctypes.c_int32),
+        ("extra_hash_bins", ctypes.c_void_p),
     ]
 
 
@@ -71,6 +74,7 @@ class xs_params(ctypes.Structure):
         ("queue", ctypes.c_int32),
         ("unroll", ctypes.c_int32),
         ("wave_per_lookup", ctypes.c_int32),
+        ("hash_bins", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -89,6 +93,10 @@ class xs_table_info_t(ctypes.Structure):
         ("reserved", ctypes.c_uint32),
         ("e_min", ctypes.c_double),
         ("e_max", ctypes.c_double),
+        ("n_hash_grids", ctypes.c_int32),
+        ("hash_bins", ctypes.c_int32 * XS_MAX_HASH_GRIDS),
+        ("reserved2", ctypes.c_int32),
+        ("checksum", ctypes.c_uint64),
         ("bytes_grid", ctypes.c_size_t),
         ("bytes_fp64", ctypes.c_size_t),
         ("bytes_fp32", ctypes.c_size_t),
@@ -98,7 +106,10 @@ class xs_table_info_t(ctypes.Structure):
     ]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        d = {f: getattr(self, f) for f, _ in self._fields_
+             if f not in ("reserved", "reserved2")}
+        d["hash_bins"] = list(self.hash_bins)[:self.n_hash_grids]
+        return d
 
 
 class xs_debug_info(ctypes.Structure):
@@ -138,12 +149,14 @@ class xs_tune_config(ctypes.Structure):
         ("batch", ctypes.c_int32),
         ("reps", ctypes.c_int32),
         ("warmup", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("active", ctypes.c_int32),
         ("timeout_factor", ctypes.c_double),
         ("kappa", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("grid_mask", ctypes.c_uint32),
         ("sort_mask", ctypes.c_uint32),
+        ("n_hash_grids", ctypes.c_int32),
+        ("hash_bins", ctypes.c_int32 * XS_MAX_HASH_GRIDS),
     ]
 
 
@@ -157,6 +170,9 @@ class xs_tune_result(ctypes.Structure):
         ("cut", ctypes.c_int32),
         ("space_size", ctypes.c_int32),
         ("best_eval", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("from_cache", ctypes.c_int32),
+        ("measured", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -164,7 +180,36 @@ class xs_tune_result(ctypes.Structure):
                 "baseline": self.baseline.as_dict(),
                 "baseline_ms": self.baseline_ms, "evaluated": self.evaluated,
                 "cut": self.cut, "space_size": self.space_size,
-                "best_eval": self.best_eval}
+                "best_eval": self.best_eval, "n": self.n,
+                "from_cache": self.from_cache, "measured": self.measured}
+
+
+class xs_tune_request(ctypes.Structure):
+    _fields_ = [
+        ("n_sizes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("sizes", ctypes.c_void_p),
+        ("d_E", ctypes.c_void_p),
+        ("d_mat", ctypes.c_void_p),
+        ("d_active", ctypes.c_void_p),
+        ("d_out", ctypes.c_void_p),
+        ("d_ws", ctypes.c_void_p),
+        ("ws_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+        ("cache_path", ctypes.c_char_p),
+        ("config", xs_tune_config),
+    ]
+
+
+class xs_tune_key(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_char * 96),
+        ("checksum", ctypes.c_uint64),
+        ("precision", ctypes.c_int32),
+        ("active", ctypes.c_int32),
+        ("size_class", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
 
 
 class xs_request(ctypes.Structure):
@@ -264,9 +309,14 @@ def load_library(path: str = LIB_PATH):
         "xs_tune_config_default": ([P(xs_tune_config)], i32),
         "xs_tune_search": ([ctypes.c_uint32, P(xs_tune_config), EVAL_FN, vp,
                             P(xs_tune_result)], i32),
-        "xs_tune": ([vp, i64, vp, vp, vp, vp, sz, vp, P(xs_tune_config),
-                     P(xs_tune_result)], i32),
-        "xs_set_tuned": ([vp, i64, P(xs_params)], i32),
+        "xs_tune": ([vp, P(xs_tune_request), P(xs_tune_result)], i32),
+        "xs_set_tuned": ([vp, i64, i32, P(xs_params)], i32),
+        "xs_tune_load": ([vp, ctypes.c_char_p, P(i32)], i32),
+        "xs_tune_key_of": ([vp, i32, i32, i64, P(xs_tune_key)], i32),
+        "xs_tune_cache_get": ([ctypes.c_char_p, P(xs_tune_key), P(xs_params),
+                               P(ctypes.c_double)], i32),
+        "xs_tune_cache_put": ([ctypes.c_char_p, P(xs_tune_key), P(xs_params),
+                               ctypes.c_double], i32),
         "xs_stream_create": ([vp, P(xs_params), i32, vp, P(vp)], i32),
         "xs_stream_submit": ([vp, P(xs_request), i32], i32),
         "xs_stream_wait": ([vp, P(xs_request_stats), P(ctypes.c_double)], i32),
@@ -317,13 +367,15 @@ def _stream_ptr(stream, device=None):
 
 def make_params(precision=XS_FP64, grid=XS_AUTO, sort=XS_AUTO, block_size=0,
                 lookups_per_thread=0, lds_stage=XS_AUTO, sort_threshold=-1,
-                queue=XS_AUTO, unroll=0, wave_per_lookup=XS_AUTO) -> xs_params:
+                queue=XS_AUTO, unroll=0, wave_per_lookup=XS_AUTO,
+                hash_bins=XS_AUTO) -> xs_params:
     if isinstance(grid, str):
         grid = GRIDS[grid]
     if isinstance(sort, str):
         sort = SORTS[sort]
     return xs_params(precision, grid, sort, block_size, lookups_per_thread,
-                     lds_stage, sort_threshold, queue, unroll, wave_per_lookup)
+                     lds_stage, sort_threshold, queue, unroll, wave_per_lookup,
+                     hash_bins)
 
 
 class Tables:
@@ -349,12 +401,15 @@ class Tables:
         return self.handle
 
 
-def make_desc(t, build_flags: int = 0, n_hash_bins: int = 0):
+def make_desc(t, build_flags: int = 0, n_hash_bins: int = 0,
+              extra_hash_bins=()):
     """xs_table_desc over host numpy arrays of a table set (any object with
     grid_offsets, energy, xs, mat_offsets, mat_nuclides, mat_density).
     Returns (desc, keep) where keep holds the arrays alive."""
     import numpy as np
+    extra = np.ascontiguousarray(list(extra_hash_bins), dtype=np.int32)
     keep = dict(
+        extra_hash_bins=extra,
         grid_offsets=np.ascontiguousarray(t.grid_offsets, dtype=np.int64),
         energy=np.ascontiguousarray(t.energy, dtype=np.float64),
         xs=np.ascontiguousarray(t.xs, dtype=np.float64).reshape(-1),
@@ -367,16 +422,19 @@ def make_desc(t, build_flags: int = 0, n_hash_bins: int = 0):
         keep["grid_offsets"].ctypes.data, keep["energy"].ctypes.data,
         keep["xs"].ctypes.data, len(keep["mat_offsets"]) - 1,
         keep["mat_offsets"].ctypes.data, keep["mat_nuclides"].ctypes.data,
-        keep["mat_density"].ctypes.data, build_flags, n_hash_bins)
+        keep["mat_density"].ctypes.data, build_flags, n_hash_bins,
+        len(extra), extra.ctypes.data if len(extra) else None)
     return d, keep
 
 
 def xs_create_tables(t, build_flags: int = XS_BUILD_FP32 | XS_BUILD_HASH,
-                     n_hash_bins: int = 4000, stream=None) -> Tables:
+                     n_hash_bins: int = 4000, stream=None,
+                     extra_hash_bins=()) -> Tables:
     """Upload a table set (see make_desc) and build the requested structures.
-    The paper's default bin count is 4,000."""
+    The paper's default bin count is 4,000; extra_hash_bins adds further hash
+    grids (the tuner's hash-bin choices)."""
     lib = load_library()
-    desc, keep = make_desc(t, build_flags, n_hash_bins)
+    desc, keep = make_desc(t, build_flags, n_hash_bins, extra_hash_bins)
     h = ctypes.c_void_p()
     s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
     _check(lib.xs_create_tables(ctypes.byref(desc), s, ctypes.byref(h)),
@@ -560,7 +618,12 @@ def xs_tune_config_default(**over) -> xs_tune_config:
     _check(load_library().xs_tune_config_default(ctypes.byref(c)),
            "xs_tune_config_default")
     for k, v in over.items():
-        setattr(c, k, v)
+        if k == "hash_bins":  # a list: the hash grids on offer
+            c.n_hash_grids = len(v)
+            for i, b in enumerate(v):
+                c.hash_bins[i] = b
+        else:
+            setattr(c, k, v)
     return c
 
 
@@ -588,37 +651,105 @@ def xs_tune_search(built_grids: int, cfg: xs_tune_config, evaluate) -> xs_tune_r
 
 
 def xs_tune(tables: Tables, E, mat, cfg: xs_tune_config = None, out=None,
-            workspace=None, stream=None) -> xs_tune_result:
-    """Tune xs_lookup_batch for len(E) lookups on these queries and record the
-    winner in the handle."""
+            workspace=None, stream=None, sizes=None, cache_path=None,
+            active=None):
+    """Tune xs_lookup_batch (or, with an active mask, xs_lookup_active) on
+    these sample queries and record the winners in the handle.  sizes: batch
+    sizes to tune (each tunes on the first n queries); None tunes len(E) and
+    returns its one xs_tune_result, else a list in the order of sizes.
+    cache_path: tuned-parameter file read before and written after."""
+    import numpy as np
     import torch
     _check_queries(E, mat)
-    n = E.numel()
     if cfg is None:
         cfg = xs_tune_config_default()
+    single = sizes is None
+    sz = np.ascontiguousarray([E.numel()] if single else list(sizes),
+                              dtype=np.int64)
+    n_max = int(sz.max())
+    if n_max > E.numel():
+        raise ValueError("a size exceeds the sample queries")
+    if active is not None:
+        if active.dtype != torch.uint8 or active.numel() < n_max:
+            raise TypeError("active must be a uint8 tensor covering the sizes")
+        cfg.active = 1
     dt = torch.float64 if cfg.precision == XS_FP64 else torch.float32
     if out is None:
-        out = torch.empty((n, XS_CHANNELS), dtype=dt, device=E.device)
+        out = torch.empty((n_max, XS_CHANNELS), dtype=dt, device=E.device)
     if workspace is None:
-        nb = xs_workspace_size(tables, n, make_params(
+        nb = xs_workspace_size(tables, n_max, make_params(
             cfg.precision, grid=XS_GRID_NUCLIDE, sort=XS_SORT_BAND_MATERIAL,
             sort_threshold=0))
         keep, ws, nb = _workspace(nb, E.device)
     else:
         keep, ws, nb = workspace
-    r = xs_tune_result()
-    _check(load_library().xs_tune(
-        tables.handle, n, ctypes.c_void_p(E.data_ptr()),
-        ctypes.c_void_p(mat.data_ptr()), ctypes.c_void_p(out.data_ptr()), ws,
-        nb, _stream_ptr(stream, E.device), ctypes.byref(cfg), ctypes.byref(r)),
-        "xs_tune")
-    return r
+    req = xs_tune_request(
+        len(sz), 0, sz.ctypes.data, E.data_ptr(), mat.data_ptr(),
+        active.data_ptr() if active is not None else None, out.data_ptr(),
+        ws.value if ws is not None else None, nb,
+        _stream_ptr(stream, E.device).value,
+        cache_path.encode() if cache_path else None, cfg)
+    res = (xs_tune_result * len(sz))()
+    _check(load_library().xs_tune(tables.handle, ctypes.byref(req), res),
+           "xs_tune")
+    return res[0] if single else list(res)
 
 
-def xs_set_tuned(tables: Tables, n: int, params: xs_params = None):
+def xs_set_tuned(tables: Tables, n: int, params: xs_params = None,
+                 active: bool = False):
     _check(load_library().xs_set_tuned(
-        tables.handle, n, ctypes.byref(params) if params is not None else None),
+        tables.handle, n, 1 if active else 0,
+        ctypes.byref(params) if params is not None else None),
         "xs_set_tuned")
+
+
+def xs_tune_load(tables: Tables, cache_path: str) -> int:
+    """Load the entries of a tuned-parameter file that match this handle and
+    device; returns how many."""
+    n = ctypes.c_int32()
+    _check(load_library().xs_tune_load(tables.handle, cache_path.encode(),
+                                       ctypes.byref(n)), "xs_tune_load")
+    return n.value
+
+
+def xs_tune_key_of(tables: Tables, precision: int, active: bool, n: int) -> xs_tune_key:
+    k = xs_tune_key()
+    _check(load_library().xs_tune_key_of(tables.handle, precision,
+                                         1 if active else 0, n,
+                                         ctypes.byref(k)), "xs_tune_key_of")
+    return k
+
+
+def make_tune_key(device: str, checksum: int, precision: int, active: bool,
+                  n: int) -> xs_tune_key:
+    """A key built on the host (no device), for xs_tune_cache_get/put."""
+    k = xs_tune_key()
+    k.device = device.encode()
+    k.checksum = checksum
+    k.precision = precision
+    k.active = 1 if active else 0
+    k.size_class = max(int(n), 1).bit_length() - 1
+    return k
+
+
+def xs_tune_cache_get(cache_path: str, key: xs_tune_key):
+    """(params, best_ms) of the key's entry, or None if the file has none."""
+    p = xs_params()
+    ms = ctypes.c_double()
+    st = load_library().xs_tune_cache_get(cache_path.encode(), ctypes.byref(key),
+                                          ctypes.byref(p), ctypes.byref(ms))
+    if st == XS_ENOTBUILT:
+        return None
+    _check(st, "xs_tune_cache_get")
+    return p, ms.value
+
+
+def xs_tune_cache_put(cache_path: str, key: xs_tune_key, params: xs_params,
+                      best_ms: float):
+    _check(load_library().xs_tune_cache_put(cache_path.encode(),
+                                            ctypes.byref(key),
+                                            ctypes.byref(params), best_ms),
+           "xs_tune_cache_put")
 
 
 class Stream:

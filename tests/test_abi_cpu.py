@@ -34,7 +34,8 @@ def test_exports_every_declared_function(lib):
 
 
 STRUCTS = ["xs_table_desc", "xs_params", "xs_table_info_t", "xs_profile_t",
-           "xs_tune_config", "xs_tune_result", "xs_request",
+           "xs_tune_config", "xs_tune_result", "xs_tune_request",
+           "xs_tune_key", "xs_request",
            "xs_request_stats", "xs_event_config", "xs_event_buffers",
            "xs_event_result", "xs_debug_info"]
 
@@ -158,6 +159,37 @@ def test_create_rejects_structure(lib):
     t3 = synth.Tables(t.grid_offsets, t.energy, t.xs, np.array([0, 2], np.int32),
                       np.array([1, 1], np.int32), np.array([1.0, 1.0]))
     assert _create_status(t3)[0] == xs.XS_ETABLE
+
+
+FP32_RANGE = {
+    "xs_overflows_fp32": dict(xs=_set(4, 3.5e38)),
+    "xs_subnormal_in_fp32": dict(xs=_set(6, 1e-39)),
+    "xs_rounds_to_zero_in_fp32": dict(xs=_set(2, 1e-50)),
+    "density_subnormal_in_fp32": dict(mat_density=_set(0, 1e-40)),
+    "density_overflows_fp32": dict(mat_density=_set(1, 1e39)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FP32_RANGE))
+def test_fp32_build_rejects_values_outside_fp32(lib, name):
+    """Values that FP32 cannot hold as normal numbers are refused when the
+    FP32 records are built, and accepted when they are not."""
+    t = _mutated(**FP32_RANGE[name])
+    st, msg, h = _create_status(t, xs.XS_BUILD_FP32)
+    assert st == xs.XS_ETABLE and "FP32" in msg, (st, msg)
+    assert not h.value
+    st, msg, _ = _create_status(t, 0)
+    assert st != xs.XS_ETABLE, msg  # FP64 tables hold them
+
+
+def test_fp32_build_accepts_zero_and_the_normal_range(lib):
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present; covered by the GPU tests")
+    t = _mutated(xs=lambda a: a.reshape(-1).__setitem__(
+        slice(0, 3), [0.0, np.finfo(np.float32).tiny, 3.0e38]))
+    st, msg, _ = _create_status(t, xs.XS_BUILD_FP32)
+    assert st == xs.XS_EHIP, (st, msg)  # past every host check
 
 
 def test_null_arguments(lib):

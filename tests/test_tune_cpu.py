@@ -47,13 +47,29 @@ class Recorder:
         self.calls.append(dict(grid=p.grid, sort=p.sort, bs=p.block_size,
                                lpt=p.lookups_per_thread, u=p.unroll,
                                thr=p.sort_threshold, lds=p.lds_stage,
-                               wave=p.wave_per_lookup, prec=p.precision))
+                               wave=p.wave_per_lookup, prec=p.precision,
+                               hb=p.hash_bins, q=p.queue))
         self.cutoffs.append(cutoff)
         return self.fn(p)
 
 
-def all_valid(calls):
+THRESHOLDS = (0, 20000, INT64_MAX)
+
+
+def all_valid(calls, hash_bins=(0,), active=False):
     for c in calls:
+        # conditional parameters (paper section 5.2): each is varied only
+        # under the value of the parameter it depends on, and holds one fixed
+        # value otherwise
+        if c["grid"] == 1:
+            assert c["hb"] in hash_bins
+        else:
+            assert c["hb"] == 0
+        if c["sort"] == 0:
+            assert c["thr"] == INT64_MAX
+        else:
+            assert c["thr"] in THRESHOLDS
+        assert c["q"] in ((0, 1) if active else (0,))
         assert c["bs"] in BLOCKS
         assert 1 <= c["lpt"] <= 8 and c["u"] in (1, 2, 4)
         assert c["u"] == 1 or c["lpt"] <= 2
@@ -64,9 +80,11 @@ def all_valid(calls):
         assert c["wave"] in (0, 1)
         assert c["wave"] == 0 or (c["lpt"] == 1 and c["u"] == 1 and
                                   c["lds"] == 0 and c["bs"] <= 256)
-        # conditional parameter: the threshold only means something when a
-        # sort is selected; it is never varied within a policy
-        assert c["thr"] == (INT64_MAX if c["sort"] == 0 else 0)
+
+
+def key_of(c):
+    return (c["grid"], c["sort"], c["bs"], c["lpt"], c["u"], c["lds"],
+            c["wave"], c["hb"], c["thr"], c["q"])
 
 
 def test_exhaustive_finds_optimum():
@@ -76,8 +94,7 @@ def test_exhaustive_finds_optimum():
     r = xs.xs_tune_search(7, cfg, rec)
     assert r.evaluated == r.space_size == len(rec.calls)
     all_valid(rec.calls)
-    keys = {(c["grid"], c["sort"], c["bs"], c["lpt"], c["u"], c["lds"],
-             c["wave"]) for c in rec.calls}
+    keys = {key_of(c) for c in rec.calls}
     assert len(keys) == len(rec.calls)  # no configuration twice
     best = min(cost_of(c) for c in rec.calls)
     assert r.best_ms == pytest.approx(best)
@@ -94,17 +111,108 @@ def cost_of(c):
     return cost(p)
 
 
-def test_space_size_matches_enumeration():
+def launch_shapes():
     n = 0
     for lpt, u in [(l, 1) for l in range(1, 9)] + [(1, 2), (2, 2), (1, 4), (2, 4)]:
         n += sum(1 for b in BLOCKS if b <= max_block(lpt, u))
     for lpt in (1, 2):  # LDS staging, three stage shapes
         n += 3 * sum(1 for b in BLOCKS if b <= 1024 // lpt)
     n += sum(1 for b in BLOCKS if b <= 256)  # one wave per lookup
+    return n
+
+
+def test_space_size_matches_enumeration():
+    """(grid, hash grid) x (no sort, or 4 policies x 3 thresholds) x launch
+    shapes, x 2 queue modes when xs_lookup_active is tuned."""
+    n = launch_shapes()
+    sorts = 1 + 4 * 3
     for grids, mult in ((7, 3), (1, 1), (5, 2)):
         cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0)
         r = xs.xs_tune_search(grids, cfg, Recorder())
-        assert r.space_size == n * 5 * mult
+        assert r.space_size == n * sorts * mult
+    for nb in (1, 3):
+        for active in (0, 1):
+            cfg = xs.xs_tune_config_default(
+                strategy=0, timeout_factor=0.0, active=active,
+                hash_bins=[4000, 8192, 32768][:nb])
+            r = xs.xs_tune_search(7, cfg, Recorder())
+            assert r.space_size == n * sorts * (2 + nb) * (2 if active else 1)
+
+
+def test_conditional_parameters_never_vary_outside_their_condition():
+    """Hash bins only under the hash grid, the threshold only under a sort,
+    the queue mode only for xs_lookup_active; every combination of the
+    active values appears."""
+    bins = [4000, 8192, 32768]
+    for active in (0, 1):
+        rec = Recorder()
+        cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0,
+                                        active=active, hash_bins=bins)
+        r = xs.xs_tune_search(7, cfg, rec)
+        assert r.evaluated == len(rec.calls) == r.space_size
+        all_valid(rec.calls, hash_bins=bins, active=bool(active))
+        assert len({key_of(c) for c in rec.calls}) == len(rec.calls)
+        hashed = [c for c in rec.calls if c["grid"] == 1]
+        assert {c["hb"] for c in hashed} == set(bins)
+        assert {c["hb"] for c in rec.calls if c["grid"] != 1} == {0}
+        sorted_ = [c for c in rec.calls if c["sort"] != 0]
+        assert {c["thr"] for c in sorted_} == set(THRESHOLDS)
+        assert {c["q"] for c in rec.calls} == ({0, 1} if active else {0})
+        # every active combination, the rest fixed
+        assert {(c["hb"], c["thr"], c["q"]) for c in hashed if c["sort"] == 4} \
+            == {(b, t, q) for b in bins for t in THRESHOLDS
+                for q in ((0, 1) if active else (0,))}
+
+
+def paper_cost(p):
+    """A synthetic runtime over the paper's own parameters: 8,192 bins best
+    among the hash grids, the threshold of 20,000 best, the queueless mode a
+    little faster."""
+    c = cost(p)
+    if p.grid == 1:
+        c *= {4000: 1.3, 8192: 0.42, 32768: 0.7}[p.hash_bins]
+    if p.sort != 0:
+        c *= {0: 1.25, 20000: 1.0, INT64_MAX: 1.6}[p.sort_threshold]
+    if p.queue == 1:
+        c *= 0.95
+    return c
+
+
+def test_forest_tunes_the_papers_parameters():
+    """With the hash-bin count, threshold and queue mode in the space (9,620
+    configurations, two of them within 5 % of the optimum, which needs the
+    one good hash grid although the hash grid is worse than the union grid
+    on average), the forest search with 96 evaluations lands within 20 % of
+    the optimum on average over 10 seeds, finds the paper parameters' best
+    values in at least 3, and beats uniform random search of the same
+    budget on average."""
+    bins = [4000, 8192, 32768]
+    allc = Recorder(paper_cost)
+    ex = xs.xs_tune_search(7, xs.xs_tune_config_default(
+        strategy=0, timeout_factor=0.0, active=1, hash_bins=bins), allc)
+    opt = ex.best_ms
+    assert ex.space_size == 9620
+    assert ex.best.grid == 1 and ex.best.hash_bins == 8192
+    assert ex.best.sort_threshold == 20000 and ex.best.queue == 1
+    costs = np.array([paper_cost(xs.make_params(
+        c["prec"], grid=c["grid"], sort=c["sort"], block_size=c["bs"],
+        lookups_per_thread=c["lpt"], unroll=c["u"], lds_stage=c["lds"],
+        wave_per_lookup=c["wave"], hash_bins=c["hb"], sort_threshold=c["thr"],
+        queue=c["q"])) for c in allc.calls])
+    got, rand, right = [], [], 0
+    for seed in range(10):
+        rec = Recorder(paper_cost)
+        r = xs.xs_tune_search(7, xs.xs_tune_config_default(
+            strategy=1, max_evals=96, seed=seed, timeout_factor=0.0, active=1,
+            hash_bins=bins), rec)
+        all_valid(rec.calls, hash_bins=bins, active=True)
+        got.append(r.best_ms / opt)
+        right += (r.best.hash_bins, r.best.sort_threshold) == (8192, 20000)
+        pick = np.random.default_rng(seed).choice(len(costs), 96, replace=False)
+        rand.append(costs[pick].min() / opt)
+    assert np.mean(got) <= 1.2
+    assert right >= 3
+    assert np.mean(got) < np.mean(rand)
 
 
 def test_timeout_rule_cuts_and_scores_at_cutoff():
@@ -115,7 +223,7 @@ def test_timeout_rule_cuts_and_scores_at_cutoff():
     r = xs.xs_tune_search(7, cfg, rec)
     base = rec.calls[0]
     assert (base["grid"], base["sort"], base["bs"], base["lpt"], base["u"],
-            base["lds"]) == (1, 4, 256, 1, 2, 0)
+            base["lds"], base["thr"]) == (1, 4, 256, 1, 2, 0, 20000)
     assert math.isinf(rec.cutoffs[0])
     t0 = cost_of(base)
     assert r.baseline_ms == pytest.approx(t0)
@@ -189,7 +297,9 @@ def test_errors():
     with pytest.raises(RuntimeError):
         xs.xs_tune_search(7, xs.xs_tune_config_default(), boom)
     for bad in (dict(kappa=-1.0), dict(strategy=7), dict(precision=3),
-                dict(reserved=1), dict(grid_mask=8)):
+                dict(active=2), dict(grid_mask=8), dict(sort_mask=32),
+                dict(hash_bins=[4000, 4000]), dict(hash_bins=[0]),
+                dict(hash_bins=[100001]), dict(n_hash_grids=9)):
         with pytest.raises(xs.XsError) as e:
             xs.xs_tune_search(7, xs.xs_tune_config_default(**bad), Recorder())
         assert e.value.status == xs.XS_EINVAL, bad
