@@ -15,7 +15,12 @@ vendor peaks, with the issue ceiling and the demand and measured HBM
 figures beside it), the serial CPU oracle's rate (best of 5, on one thread
 and on every thread of the process's CPU share) and the comparison of both
 timed outputs with the oracle on every lookup of the batch; the run exits
-with status 1 if either differs beyond its bar.
+with status 1 if either differs beyond its bar.  After the timed steps (and
+outside `value`), `extras` carries the particles-in-flight sweep (1e5 to
+8e6 lookups, the FP32 form tuned per size over the launch shapes and the
+paper's tunables) and the uneven request stream (the persistent
+graph-launched kernel against per-request launches, p50/p99 latency) in
+brief, each checked against the oracle on samples (--no-extras skips them).
 """
 from __future__ import annotations
 
@@ -315,43 +320,59 @@ def _pctl(v, q):
     return v[min(len(v) - 1, int(round(q * (len(v) - 1))))] if v else 0.0
 
 
-def sweep_in_flight(args, torch, synth, xs):
-    """Config 4: batches of 1e5 ... 8e6 lookups on the full-size tables; per
-    batch size the FP32 form is tuned (forest search) and timed, eagerly and
-    as one captured HIP graph replayed (no launch overhead per kernel),
-    beside the plain FP64 lookup and the FP32 form under each sort policy at
-    the tuned launch shape.  One JSON line per batch size."""
-    t = synth.config2_tables()
-    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
-    extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
-    h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
-    for i, n in enumerate((100_000, 500_000, 1_000_000, 2_000_000, 4_000_000,
-                           8_000_000)):
-        q = synth.config4_queries(i, n)
-        E = torch.from_numpy(q.E).to("cuda:0")
-        m = torch.from_numpy(q.mat).to("cuda:0")
-        nbar = synth.mean_nuclides(t, q)
-        ws = xs._workspace(xs.xs_workspace_size(h, n, xs.make_params(
-            sort="band_material", sort_threshold=0)), E.device)
+IN_FLIGHT = (100_000, 500_000, 1_000_000, 2_000_000, 4_000_000, 8_000_000)
 
-        def rate(p):
-            out = torch.empty((n, 5), device="cuda:0", dtype=torch.float64
-                              if p.precision == 0 else torch.float32)
-            sec = time_steps(lambda: xs.xs_lookup_batch(
-                h, E, m, out=out, params=p, workspace=ws),
-                args.steps, args.warmup)
-            return n / sec
 
-        cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
-                                        max_evals=args.tune_evals, reps=3)
-        r = xs.xs_tune(h, E, m, cfg, workspace=ws, sizes=[n],
-                       cache_path=args.tune_cache)[0]
-        best = r.best
+def in_flight_row(args, torch, synth, xs, h, t, i, n, full=True):
+    """One batch size of the particles-in-flight sweep (config 4): the FP32
+    form tuned for this size (forest search over the launch shapes and the
+    paper's tunables: hash-bin count, sort threshold), timed, and checked
+    against the oracle's FP32 form on 20,000 sampled lookups (bit for bit);
+    plain FP64 beside it.  `full` adds the captured-graph replay and every
+    sort policy at the tuned launch shape."""
+    import oracle
+    q = synth.config4_queries(i, n)
+    E = torch.from_numpy(q.E).to("cuda:0")
+    m = torch.from_numpy(q.mat).to("cuda:0")
+    nbar = synth.mean_nuclides(t, q)
+    ws = xs._workspace(xs.xs_workspace_size(h, n, xs.make_params(
+        sort="band_material", sort_threshold=0)), E.device)
+    outs = {0: torch.empty((n, 5), device="cuda:0", dtype=torch.float64),
+            1: torch.empty((n, 5), device="cuda:0", dtype=torch.float32)}
+    steps = args.steps if full else max(3, args.steps // 2)
+
+    def rate(p):
+        sec = time_steps(lambda: xs.xs_lookup_batch(
+            h, E, m, out=outs[p.precision], params=p, workspace=ws),
+            steps, args.warmup)
+        return n / sec
+
+    cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
+                                    max_evals=args.tune_evals, reps=3)
+    r = xs.xs_tune(h, E, m, cfg, workspace=ws, sizes=[n],
+                   cache_path=args.tune_cache)[0]
+    best = xs.xs_resolve_params(h, n, r.best)
+    row = {"n": n, "mean_nuclides": nbar, "tuned": best.as_dict(),
+           "tuned_lookups_per_s": rate(best),
+           "tuned_hash_bins": best.hash_bins,
+           "tuned_sort_threshold": best.sort_threshold,
+           "tuner": {"evaluated": r.evaluated, "measured": r.measured,
+                     "cut": r.cut, "best_eval": r.best_eval,
+                     "space_size": r.space_size,
+                     "from_cache": r.from_cache}}
+    pick = np.unique(synth.Stream(43, i).integers(20_000, 0, n - 1))
+    got = outs[1].cpu().numpy()[pick]
+    ref32 = oracle.lookup_f32(t, q.E[pick], q.mat[pick],
+                              threads=host_cpus()["threads"])
+    row["tuned_equals_oracle_on_sample"] = bool(np.array_equal(got, ref32))
+    plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
+                           block_size=256, lookups_per_thread=1, unroll=1,
+                           lds_stage=0, sort_threshold=xs.INT64_MAX)
+    row["plain_fp64_lookups_per_s"] = rate(plain)
+    if full:
         def graph_rate(p):
             """The same call captured once in a HIP graph and replayed."""
-            out = torch.empty((n, 5), device="cuda:0", dtype=torch.float64
-                              if p.precision == 0 else torch.float32)
+            out = outs[p.precision]
             side = torch.cuda.Stream()
             side.wait_stream(torch.cuda.current_stream())
             with torch.cuda.stream(side):
@@ -363,20 +384,7 @@ def sweep_in_flight(args, torch, synth, xs):
             sec = time_steps(g.replay, args.steps, args.warmup)
             del g
             return n / sec
-
-        row = {"n": n, "mean_nuclides": nbar, "tuned": best.as_dict(),
-               "tuned_lookups_per_s": rate(best),
-               "tuned_graph_lookups_per_s": graph_rate(best),
-               "tuned_hash_bins": best.hash_bins,
-               "tuned_sort_threshold": best.sort_threshold,
-               "tuner": {"evaluated": r.evaluated, "measured": r.measured,
-                         "cut": r.cut, "best_eval": r.best_eval,
-                         "space_size": r.space_size,
-                         "from_cache": r.from_cache}}
-        plain = xs.make_params(xs.XS_FP64, grid="nuclide", sort="none",
-                               block_size=256, lookups_per_thread=1, unroll=1,
-                               lds_stage=0, sort_threshold=xs.INT64_MAX)
-        row["plain_fp64_lookups_per_s"] = rate(plain)
+        row["tuned_graph_lookups_per_s"] = graph_rate(best)
         for name, sp in xs.SORTS.items():
             p = xs.xs_params()
             p.precision, p.grid, p.sort = best.precision, best.grid, sp
@@ -386,11 +394,29 @@ def sweep_in_flight(args, torch, synth, xs):
             p.hash_bins = best.hash_bins
             p.sort_threshold = 0 if sp else xs.INT64_MAX
             row[f"fp32_sort_{name}_lookups_per_s"] = rate(p)
+    log(f"n={n}: tuned {row['tuned_lookups_per_s']:.4g}/s "
+        f"({best.as_dict()}), plain FP64 {row['plain_fp64_lookups_per_s']:.4g}/s")
+    return row
+
+
+def sweep_in_flight(args, torch, synth, xs):
+    """Config 4: batches of 1e5 ... 8e6 lookups on the full-size tables, with
+    hash grids of 4,000, 8,192 and 32,768 bins; per batch size the FP32 form
+    is tuned and timed, eagerly and as one captured HIP graph replayed, beside
+    the plain FP64 lookup and the FP32 form under each sort policy at the
+    tuned launch shape.  One JSON line per batch size."""
+    t = synth.config2_tables()
+    flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
+             xs.XS_BUILD_UNION_BY_MATERIAL)
+    extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
+    h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
+    ok = True
+    for i, n in enumerate(IN_FLIGHT):
+        row = in_flight_row(args, torch, synth, xs, h, t, i, n, full=True)
+        ok = ok and row["tuned_equals_oracle_on_sample"]
         print(json.dumps(row), flush=True)
-        log(f"n={n}: tuned {row['tuned_lookups_per_s']:.4g}/s "
-            f"({best.as_dict()}), plain FP64 {row['plain_fp64_lookups_per_s']:.4g}/s")
     h.close()
-    return 0
+    return 0 if ok else 1
 
 
 def request_stream(args, torch, synth, xs):
@@ -409,8 +435,25 @@ def request_stream(args, torch, synth, xs):
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
              xs.XS_BUILD_UNION_BY_MATERIAL)
     h = xs.xs_create_tables(t, flags, args.bins)
+    line, ok = request_stream_line(
+        args, torch, synth, xs, h, t, args.stream_requests,
+        (1_000, 10_000, 100_000, 1_000_000, 10_000_000))
+    print(json.dumps(line), flush=True)
+    h.close()
+    if not ok:
+        log("PARITY FAILURE in the request-stream forms")
+        return 1
+    return 0
+
+
+def request_stream_line(args, torch, synth, xs, h, t, n_requests,
+                        tune_classes):
+    """The request-stream measurements on handle h (see request_stream):
+    the first n_requests requests of the stream; the FP32 form is tuned for
+    each size in tune_classes first (classes tuned earlier on h are
+    reused).  Returns (JSON-ready dict, every parity check passed)."""
     log("generating the request stream")
-    sizes, q = synth.config5_requests(args.stream_requests)
+    sizes, q = synth.config5_requests(n_requests)
     total = int(sizes.sum())
     E = torch.from_numpy(q.E).to("cuda:0")
     m = torch.from_numpy(q.mat).to("cuda:0")
@@ -418,8 +461,10 @@ def request_stream(args, torch, synth, xs):
     offs = np.concatenate(([0], np.cumsum(sizes)))
     log(f"{len(sizes)} requests, {total} lookups")
 
-    # Tune the FP32 form per size class (10^3 .. 10^6) on slices of the stream.
-    for n in (1_000, 10_000, 100_000, 1_000_000, 10_000_000):
+    # Tune the FP32 form per size class on slices of the stream.
+    for n in tune_classes:
+        if n > total:
+            continue
         cfg = xs.xs_tune_config_default(precision=xs.XS_FP32,
                                         max_evals=args.tune_evals, reps=3)
         r = xs.xs_tune(h, E[:n], m[:n], cfg)
@@ -519,12 +564,7 @@ def request_stream(args, torch, synth, xs):
             "stream_params": p_stream.as_dict(),
             "bit_identical_to_per_request_launches": same,
             "per_request_launches_equal_oracle_on_sample": oracle_ok}
-    print(json.dumps(line), flush=True)
-    h.close()
-    if not (oracle_ok and all(same.values())):
-        log("PARITY FAILURE in the request-stream forms")
-        return 1
-    return 0
+    return line, bool(oracle_ok and all(same.values()))
 
 
 def tuner_study(args, torch, synth, xs):
@@ -843,6 +883,11 @@ def main(argv=None):
                     help="2: the headline line (default); 4: particles-in-"
                          "flight sweep; 5: uneven request stream")
     ap.add_argument("--stream-requests", type=int, default=2000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the brief particles-in-flight sweep and request "
+                    "stream that follow the timed steps")
+    ap.add_argument("--extras-requests", type=int, default=100,
+                    help="requests of the stream in the extras")
     ap.add_argument("--tuner-study", action="store_true",
                     help="exhaustive vs forest vs random search on the "
                          "tuning space (evaluations to the optimum)")
@@ -859,6 +904,9 @@ def main(argv=None):
     ap.add_argument("--energy", action="store_true",
                     help="run time / energy / EDP of the lookup and tuning "
                          "for each objective (board energy accumulator)")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="the achievable rate of random 32-128-byte reads "
+                    "(paper_2402_09222_amd/probes/gather_probe.hip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain device copy of 2 GiB and exit (the "
                          "achievable-bandwidth figure and the reference for "
@@ -873,6 +921,20 @@ def main(argv=None):
     import torch
     import synth
     from paper_2402_09222_amd import xs
+
+    if args.gather_probe:
+        import subprocess
+        exe = os.path.join(ROOT, "paper_2402_09222_amd", "gather_probe")
+        if not os.path.exists(exe):
+            raise RuntimeError(f"{exe} is missing: run __graft_entry__.build()")
+        for mib in (128, 512):
+            r = subprocess.run([exe, str(max(args.steps, 3)), str(mib)],
+                               capture_output=True, text=True, timeout=120)
+            if r.returncode != 0:
+                log(r.stderr)
+                return 1
+            print(r.stdout.strip(), flush=True)
+        return 0
 
     if args.copy_probe:
         nbytes = 2 << 30
@@ -906,8 +968,9 @@ def main(argv=None):
     flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH
     if not args.no_union:
         flags |= xs.XS_BUILD_UNIONIZED | xs.XS_BUILD_UNION_BY_MATERIAL
+    extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
     t0 = time.perf_counter()
-    h = xs.xs_create_tables(t, flags, args.bins)
+    h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
     build_s = time.perf_counter() - t0
     info = xs.xs_table_info(h)
     log(f"tables built in {build_s:.2f} s; mean nuclides per lookup {nbar:.2f}")
@@ -1009,6 +1072,25 @@ def main(argv=None):
             log(f"parity {k}: ok={v['ok']} max rel per channel "
                 + " ".join(f"{x:.3g}" for x in v["max_rel"]))
 
+    # The particles-in-flight sweep and the request stream in brief, after
+    # the timed steps (they do not enter `value`).
+    extras = None
+    extras_ok = True
+    if not args.no_extras and args.only is None and not args.params:
+        extras = {"in_flight": []}
+        log("extras: particles-in-flight sweep")
+        for i, nn in enumerate(IN_FLIGHT):
+            row = in_flight_row(args, torch, synth, xs, h, t, i, nn,
+                                full=False)
+            extras_ok = extras_ok and row["tuned_equals_oracle_on_sample"]
+            extras["in_flight"].append(row)
+        log(f"extras: request stream ({args.extras_requests} requests)")
+        st_line, st_ok = request_stream_line(
+            args, torch, synth, xs, h, t, args.extras_requests,
+            (1_000, 10_000))
+        extras["request_stream"] = st_line
+        extras_ok = extras_ok and st_ok
+
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -1027,7 +1109,7 @@ def main(argv=None):
                          "points, 12 materials (4-321 nuclides), "
                          f"{n} lookups, E log-uniform, m uniform"),
             "n_lookups": n, "mean_nuclides": nbar,
-            "hash_bins": args.bins, "union_size": info["union_size"],
+            "hash_bins": info["hash_bins"], "union_size": info["union_size"],
             "table_build_s": build_s,
         },
         "roofline": head["roofline"],
@@ -1038,10 +1120,15 @@ def main(argv=None):
     }
     if plain and tuned:
         line["fp32_tuned_over_fp64_plain"] = tuned["value"] / plain["value"]
+    if extras is not None:
+        line["extras"] = extras
     print(json.dumps(line), flush=True)
     h.close()
     if parity is not None and not all(v["ok"] for v in parity.values()):
         log("PARITY FAILURE: the timed outputs differ from the oracle")
+        return 1
+    if not extras_ok:
+        log("PARITY FAILURE in the extras (in-flight sweep or request stream)")
         return 1
     return 0
 

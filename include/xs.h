@@ -140,12 +140,13 @@ typedef struct {
 /* Launch and method parameters of one lookup call.  Every field except
  * `precision` may be XS_AUTO (or 0 for block_size / lookups_per_thread), in
  * which case the value recorded by xs_tune for this precision and batch size
- * is used, else the library default: for n >= 262,144 (one query per lane
- * of the chip) grid HASH if built else NUCLIDE, sort BAND_MATERIAL at
- * n >= 20,000, block 256, 1 lookup per thread, 2 nuclides in flight; for
- * smaller n one wave per lookup, grid UNIONIZED if built, unsorted, block
- * 128.  An XS_AUTO wave_per_lookup becomes 0 wherever the fields set
- * explicitly exclude it.  The
+ * is used, else the library default: grid UNIONIZED if built, else HASH if
+ * built, else NUCLIDE; block 128, 1 lookup per thread, 1 nuclide in flight;
+ * for n >= 262,144 (one query per lane of the chip) sort BAND_MATERIAL at
+ * n >= 20,000 and LDS stage shape 3 below 1.5M lookups, 2 below 3M, 1
+ * above; for smaller n one wave per lookup, unsorted.  An XS_AUTO
+ * wave_per_lookup or lds_stage becomes 0 wherever the fields set explicitly
+ * exclude it.  The
  * choice never changes the results: every combination returns the same
  * indices and, within one precision, bit-identical sums. */
 typedef struct {

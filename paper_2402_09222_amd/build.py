@@ -21,6 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libxs.so")
+PROBE = os.path.join(HERE, "gather_probe")
 ARCH = os.environ.get("XS_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -61,7 +62,24 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The random-gather probe (probes/gather_probe.hip): a stand-alone
+    executable that bench.py --gather-probe runs for the achievable rate of
+    scattered reads."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, *CXXFLAGS, os.path.join(HERE, "probes", "gather_probe.hip"),
+           "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the gather probe:\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":

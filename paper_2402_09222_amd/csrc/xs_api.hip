@@ -302,7 +302,14 @@ xs_status resolve(xs_tables_s* h, int64_t n, const xs_params* in,
   if (p.block_size == 0 || p.block_size == XS_AUTO) p.block_size = t.block_size;
   if (p.lookups_per_thread == 0 || p.lookups_per_thread == XS_AUTO)
     p.lookups_per_thread = t.lookups_per_thread;
-  if (p.lds_stage == XS_AUTO) p.lds_stage = t.lds_stage;
+  if (p.lds_stage == XS_AUTO) {
+    // only where the fields set explicitly allow it
+    const bool fits = p.lookups_per_thread <= 2 &&
+                      (p.unroll == 0 || p.unroll == XS_AUTO || p.unroll == 1) &&
+                      p.block_size <= 1024 / p.lookups_per_thread &&
+                      p.wave_per_lookup != 1;
+    p.lds_stage = fits ? t.lds_stage : 0;
+  }
   if (p.wave_per_lookup == XS_AUTO) {
     // only where the fields set explicitly allow it
     const bool fits = p.lookups_per_thread == 1 && p.lds_stage == 0 &&
@@ -570,26 +577,28 @@ constexpr int64_t kWaveDefaultBelow = 256 * 1024;
 
 void untuned_defaults(const xs_tables_s* h, int64_t n, int precision,
                       xs_params* out) {
+  // The shapes the tuner picks on the full-size workload: the union grid
+  // (else the hash grid, else bisection), the banded sort at the paper's
+  // threshold, 128-lane blocks staging windows in LDS, with wider windows
+  // for sparser batches (shape 3 below 1.5M lookups, 2 below 3M, 1 above).
   xs_params t{};
   t.precision = precision;
-  t.grid = h->d.B > 0 ? XS_GRID_HASH : XS_GRID_NUCLIDE;
+  t.grid = h->d.U > 0 ? XS_GRID_UNIONIZED
+                      : (h->d.B > 0 ? XS_GRID_HASH : XS_GRID_NUCLIDE);
   t.sort = XS_SORT_BAND_MATERIAL;
-  t.block_size = 256;
+  t.block_size = 128;
   t.lookups_per_thread = 1;
-  t.lds_stage = 0;
+  t.lds_stage = n < 1500000 ? 3 : (n < 3000000 ? 2 : 1);
   t.sort_threshold = 20000;
   t.queue = XS_QUEUE_COMPACT;
-  t.unroll = 2;
+  t.unroll = 1;
   t.wave_per_lookup = 0;
   t.hash_bins = t.grid == XS_GRID_HASH ? h->d.B : 0;
   if (n < kWaveDefaultBelow) {
     // Too few queries to give every lane of the chip one: a wave per
-    // query, unsorted, on the fastest grid that was built.
-    t.grid = h->d.U > 0 ? XS_GRID_UNIONIZED : t.grid;
-    t.hash_bins = t.grid == XS_GRID_HASH ? h->d.B : 0;
+    // query, unsorted.
     t.sort = XS_SORT_NONE;
-    t.block_size = 128;
-    t.unroll = 1;
+    t.lds_stage = 0;
     t.wave_per_lookup = 1;
   }
   *out = t;

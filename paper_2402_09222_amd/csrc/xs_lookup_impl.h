@@ -189,6 +189,32 @@ __device__ __forceinline__ int union_row(const DevTables& t, double e) {
   return ok ? j : bisect_le(t.u, U, e);
 }
 
+// union_row for a whole wave searching one energy (every lane passes the
+// same e): the bin's edge brackets take one scalar load; then lane i reads
+// union point lo + i for the bin's points and the one after them (one round
+// of contiguous loads), and the count of points <= e, a prefix since the
+// grid is sorted, is the bracket.  That count is exact when it ends inside
+// the points read (or at the grid's ends); otherwise (the rounding of log
+// put E in a neighbouring bin, or a bin holds 64 points or more) the wave
+// searches the whole grid.  Two dependent loads instead of union_row's
+// eight (bin edges, six bisection probes over ~32 points, the verify).
+__device__ __forceinline__ int wave_union_row(const DevTables& t, double e,
+                                              int lane) {
+  double x = (log(e) - t.u_ln_min) * t.u_inv_dln;
+  x = fmin(fmax(x, 0.0), (double)(t.UB - 1));
+  const int b = (int)x;
+  const int lo = ld_const(t.uh + b), hi = ld_const(t.uh + b + 1);
+  const int U = (int)t.U;
+  const int np = min(hi + 2, U) - lo;  // points lo .. min(hi + 1, U - 1)
+  if (np <= 64) {
+    const int p = lo + lane;
+    const int c = __popcll(__ballot(lane < np && t.u[p] <= e));
+    if (c >= 1 && (c < np || lo + np == U)) return lo + c - 1;
+    if (c == 0 && lo == 0) return 0;
+  }
+  return wave_bisect_le(t.u, U, e, lane);
+}
+
 // Row j of the index table: [U][K] (column = nuclide id) or, when built by
 // material, material m's block [U][L_m] (column = position in m's list).
 template <>
@@ -943,12 +969,16 @@ __global__ __launch_bounds__(kWaveBlock) void k_lookup_wave(const DevTables t,
     if (lane == 0) Acc<PREC>::store_nan(a.out, o);
     return;
   }
-  // Every lane bisects the union grid for the same energy, so each probe is
-  // one broadcast load (measured faster here than wave_bisect_le, whose 64
-  // distinct lines per step cost more than its shorter chain saves when
-  // every wave searches).
+  // Every lane searches the union grid for the same energy: the logarithmic
+  // bin, then one contiguous read of the bin's points (wave_union_row).  (A
+  // 64-way search of the whole grid, wave_bisect_le, was slower here: with
+  // every wave searching, its 64 lines per step cost more than its shorter
+  // chain saved.)
   Locator<GRID> loc;
-  loc.init(t, e, m);
+  if constexpr (GRID == XS_GRID_UNIONIZED)
+    loc.init_row(t, wave_union_row(t, e, lane), m);
+  else
+    loc.init(t, e, m);
   Chan<PREC> sum;  // lanes 0..4: channel `lane`
   const int j0 = t.moff[m], j1 = t.moff[m + 1];
   for (int jc = j0; jc < j1; jc += 64) {

@@ -154,10 +154,23 @@ def test_default_params(cfg1):
     out = xs.xs_lookup_batch(cfg1["h"], cfg1["E"], cfg1["m"])
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), cfg1["ref"])
-    p = xs.xs_resolve_params(cfg1["h"], 300000)
-    assert p.grid == xs.XS_GRID_HASH and p.block_size == 256
-    assert p.sort == xs.XS_SORT_BAND_MATERIAL and p.unroll == 2
-    assert p.wave_per_lookup == 0
+    # one query per lane or more: banded sort, LDS-staged windows (wider
+    # ones for sparser batches), union grid when built
+    for n, shape in ((300000, 3), (2000000, 2), (10000000, 1)):
+        p = xs.xs_resolve_params(cfg1["h"], n)
+        assert p.grid == xs.XS_GRID_UNIONIZED and p.block_size == 128
+        assert p.sort == xs.XS_SORT_BAND_MATERIAL and p.unroll == 1
+        assert p.lds_stage == shape and p.wave_per_lookup == 0
+        assert p.sort_threshold == 20000 and p.lookups_per_thread == 1
+    # explicit fields that exclude staging keep one lane per query unstaged
+    for kw in (dict(lookups_per_thread=4), dict(unroll=2),
+               dict(wave_per_lookup=1, block_size=128)):
+        p = xs.xs_resolve_params(cfg1["h"], 300000, xs.make_params(**kw))
+        assert p.lds_stage == 0, kw
+    out = xs.xs_lookup_batch(cfg1["h"], cfg1["E"], cfg1["m"],
+                             params=xs.make_params(lookups_per_thread=4))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), cfg1["ref"])
     # fewer queries than lanes on the chip: one wave per query, unsorted
     p = xs.xs_resolve_params(cfg1["h"], 100000)
     assert p.grid == xs.XS_GRID_UNIONIZED and p.block_size == 128
@@ -496,5 +509,45 @@ def test_worked_examples_exact(golden):
             torch.cuda.synchronize()
             want_idx = np.concatenate([q[2] for q in queries] * reps)
             assert np.array_equal(idx.cpu().numpy(), want_idx), (golden, grid)
+    finally:
+        h.close()
+
+
+def test_wave_union_search_dense_and_sparse_bins():
+    """The wave kernel's union search reads one logarithmic bin's points at
+    once; a bin holding 64 points or more, and energies that the rounding of
+    log puts in a neighbouring bin, take the whole-grid search instead.  A
+    table with a dense cluster (2,000 points within 0.1 % of 1e-3) and long
+    empty stretches exercises both; every form returns the oracle's bits."""
+    import synth
+    say("wave union dense bins")
+    t = synth.random_tables(17, 6, [300, 40, 2000, 7, 120, 2], 5,
+                            sizes=[6, 1, 3, 4, 2])
+    k = 2  # the third nuclide: 2,000 points packed near 1e-3
+    a, b = t.grid_offsets[k], t.grid_offsets[k + 1]
+    e = np.array(t.energy, dtype=np.float64)
+    e[a] = 1e-5
+    e[b - 1] = 1.0
+    e[a + 1:b - 1] = 1e-3 * (1.0 + np.linspace(0.0, 1e-3, b - a - 2))
+    t = synth.Tables(t.grid_offsets, e, t.xs, t.mat_offsets, t.mat_nuclides,
+                     t.mat_density)
+    h = xs.xs_create_tables(t, ALL_FLAGS, 4000)
+    try:
+        u = np.unique(e)
+        near = np.concatenate([e[a:b:37], np.nextafter(e[a:b:37], 0),
+                               np.nextafter(e[a:b:37], np.inf),
+                               u[::5], np.nextafter(u[::5], 0)])
+        q = synth.random_queries(18, t, 30_000)
+        E = np.concatenate([q.E, near[(near > 0) & np.isfinite(near)]])
+        m = (np.arange(len(E)) % t.n_materials).astype(np.int32)
+        ref = oracle.lookup(t, E, m)
+        ref32 = oracle.lookup_f32(t, E, m)
+        Ed, md = dev(E, torch.float64), dev(m, torch.int32)
+        for prec, want in ((xs.XS_FP64, ref), (xs.XS_FP32, ref32)):
+            for bs in (64, 256):
+                out = run(h, Ed, md, precision=prec, grid="unionized",
+                          sort="none", block_size=bs, lookups_per_thread=1,
+                          unroll=1, lds_stage=0, wave_per_lookup=1)
+                assert np.array_equal(out, want), (prec, bs)
     finally:
         h.close()
