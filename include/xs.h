@@ -111,7 +111,9 @@ typedef struct xs_tables_s* xs_tables_t;
  *  - mat_density: finite and > 0;
  *  - with XS_BUILD_FP32, every nonzero channel value and every density must
  *    round to a normal finite FP32 number (about 1.2e-38 to 3.4e38), since
- *    the FP32 form's relative error bound holds only there;
+ *    the FP32 form's relative error bound holds only there, and so must the
+ *    reciprocal of every spacing of neighbouring grid energies (spacings of
+ *    about 3e-39 to 8e37; the FP32 records carry it);
  *  - n_hash_bins in [1, 100000] when XS_BUILD_HASH is set (the paper's range
  *    is 100 to 100k; 1 bin makes every search a full bisection);
  *  - with XS_BUILD_HASH, n_extra_hash_grids in [0, XS_MAX_HASH_GRIDS - 1]

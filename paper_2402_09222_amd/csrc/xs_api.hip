@@ -210,6 +210,11 @@ xs_status validate_desc(const xs_table_desc* d) {
       if (p > a && !(d->energy[p - 1] < e))
         return fail(XS_ETABLE, "nuclide %d: energies not strictly increasing "
                     "at point %lld", k, (long long)(p - a));
+      if (fp32 && p > a && !fp32_normal_or_zero(1.0 / (e - d->energy[p - 1])))
+        return fail(XS_ETABLE, "nuclide %d point %lld: the spacing %g of its "
+                    "energies has no normal FP32 reciprocal (XS_BUILD_FP32 "
+                    "needs spacings between about 3e-39 and 8e37)", k,
+                    (long long)(p - a), e - d->energy[p - 1]);
       for (int c = 0; c < XS_CHANNELS; ++c) {
         const double x = d->xs[p * XS_CHANNELS + c];
         if (!std::isfinite(x) || x < 0.0)
@@ -647,10 +652,16 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
     if (!rec32.empty()) {
       for (int c = 0; c < XS_CHANNELS; ++c)
         rec32[p].x[c] = (float)desc->xs[p * 5 + c];
-      rec32[p].pad = 0.0f;
+      rec32[p].rcp = 0.0f;
       rec32[p].e = desc->energy[p];
     }
   }
+  // Each FP32 record carries RN32(1 / d) of the interval it starts, d being
+  // the FP64 difference the kernels form (the seed of their division).
+  if (!rec32.empty())
+    for (int k = 0; k < K; ++k)
+      for (int64_t p = goff[k]; p + 1 < goff[k + 1]; ++p)
+        rec32[p].rcp = (float)(1.0 / (desc->energy[p + 1] - desc->energy[p]));
   std::vector<MatRec> mrec(L);
   int max_L = 0;
   for (int m = 0; m < M; ++m) {

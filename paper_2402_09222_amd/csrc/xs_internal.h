@@ -26,7 +26,9 @@ struct alignas(16) Rec64 {  // 48 bytes
 };
 struct alignas(16) Rec32 {  // 32 bytes
   float x[XS_CHANNELS];
-  float pad;
+  float rcp;  // RN32(1 / (E[p+1] - E[p])): the seed of the fraction's
+              // division for the interval this point starts (0 at a
+              // nuclide's last point)
   double e;
 };
 static_assert(sizeof(Rec64) == 48, "Rec64 layout");

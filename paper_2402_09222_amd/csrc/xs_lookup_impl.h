@@ -249,11 +249,15 @@ struct Locator<XS_GRID_UNIONIZED> {
 // move the loads that produced them past it (used to keep LDS reads and
 // global reads of the same record type in their own branches instead of
 // merging them into one load through a generic pointer).
+// The FP32 record's reciprocal is pinned only where it is used (the lower
+// record of a bracket).
 template <class R>
-__device__ __forceinline__ void pin_rec(R& r) {
+__device__ __forceinline__ void pin_rec(R& r, bool with_rcp) {
 #pragma unroll
   for (int k = 0; k < XS_CHANNELS; ++k) asm volatile("" : "+v"(r.x[k]));
   asm volatile("" : "+v"(r.e));
+  if constexpr (sizeof(R) == sizeof(Rec32))
+    if (with_rcp) asm volatile("" : "+v"(r.rcp));
 }
 
 // Field-wise out = c ? a : b.  Selecting whole records by reference would
@@ -264,6 +268,7 @@ __device__ __forceinline__ void select_rec(bool c, const R& a, const R& b,
 #pragma unroll
   for (int k = 0; k < XS_CHANNELS; ++k) out.x[k] = c ? a.x[k] : b.x[k];
   out.e = c ? a.e : b.e;
+  if constexpr (sizeof(R) == sizeof(Rec32)) out.rcp = c ? a.rcp : b.rcp;
 }
 
 // Records around a candidate index: three for the hash grid (candidate and
@@ -335,12 +340,33 @@ __device__ __forceinline__ double div_in_range(double n, double d) {
   return __builtin_fma(rem, r, q);
 }
 
+// The same correctly rounded quotient when a 24-bit approximation of 1 / d
+// is at hand (the FP32 records carry RN32(1 / d) for their interval): two
+// Newton steps take it from 2^-24 to well below the last bit of the double
+// reciprocal, as from the hardware reciprocal, and the quotient and its
+// residual correction follow unchanged.  Saves the reciprocal instruction.
+__device__ __forceinline__ double div_seeded(double n, double d, float seed) {
+  double r = (double)seed;
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  const double q = n * r;
+  const double rem = __builtin_fma(-d, q, n);
+  return __builtin_fma(rem, r, q);
+}
+
 // Clamped energy and fraction.  min(max(E, E_k[0]), E_k[n-1]) equals
 // min(max(E, E_k[i]), E_k[i+1]) for the bracket i, so only the bracket's
 // own energies are needed.
 __device__ __forceinline__ double fraction(double e, double e0, double e1) {
   const double eh = min_nonnan(max_nonnan(e, e0), e1);
   return div_in_range(eh - e0, e1 - e0);
+}
+__device__ __forceinline__ double fraction(double e, double e0, double e1,
+                                           float rcp) {
+  const double eh = min_nonnan(max_nonnan(e, e0), e1);
+  return div_seeded(eh - e0, e1 - e0, rcp);
 }
 
 // ---- accumulators and output per precision --------------------------------
@@ -415,7 +441,7 @@ struct Acc<XS_FP32> {
   __device__ __forceinline__ static void terms(const Rec32& lo, const Rec32& hi,
                                                double e, float rho,
                                                float (&t)[XS_CHANNELS]) {
-    const double f = fraction(e, lo.e, hi.e);
+    const double f = fraction(e, lo.e, hi.e, lo.rcp);
     const float f32 = (float)f;
     const float g32 = (float)(1.0 - f);
 #pragma unroll
@@ -746,8 +772,9 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
   constexpr int kLdsGroup = lds_group<SHAPE>();
   constexpr int kLdsW = lds_window<PREC, SHAPE>();
   __shared__ R stage[kLdsGroup * kLdsW];
-  __shared__ int s_first[kLdsGroup];  // first staged record, or -1: per lane
-  __shared__ int s_width[kLdsGroup];  // records in the window
+  __shared__ int s_first[kLdsGroup];  // first staged record
+  // records in the staged window (0: too wide, each lane searches itself)
+  __shared__ __align__(8) int s_win[kLdsGroup];
   __shared__ int s_mat;
   __shared__ int64_t s_row[2];
   __shared__ double s_red[2][16];
@@ -861,44 +888,56 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
       const int lo = exact_bracket(t, edge_lo, r, jg + tid, lo_e);
       const int hi = exact_bracket(t, edge_hi, r, jg + tid, hi_e);
       const int width = hi - lo + 2;  // grid points lo .. hi + 1
-      s_first[tid] = width <= kLdsW ? r.base + lo : -1;
-      s_width[tid] = width;
+      s_first[tid] = r.base + lo;
+      s_win[tid] = width <= kLdsW ? width : 0;
     }
     __syncthreads();
     for (int s = tid; s < cnt * kLdsW; s += blockDim.x) {
       const int i = s / kLdsW, k = s % kLdsW;
-      const int first_rec = s_first[i];
-      if (first_rec >= 0 && k < s_width[i]) stage[s] = recs[first_rec + k];
+      if (k < s_win[i]) stage[s] = recs[s_first[i] + k];
     }
     __syncthreads();
     // One nuclide of the group: its records (from LDS, or the lane's own
     // search when the window was too wide), then the arithmetic.
-    auto step = [&](int i) {
+    // `width` is the block-uniform s_win[i], held in a scalar register so
+    // the branch and the probe count cost no vector instructions.
+    auto step = [&](int i, int width) {
       const int j = jg + i;
       const MatRec r = ld_const(t.mrec + j);
       const auto rho = Acc<PREC>::rho(t, r, j);
       R lo[LPT], hi[LPT];
-      if (s_first[i] >= 0) {
+      if (width > 0) {
         // the record p in [0, width-2] with the largest win[p].e <= e,
-        // else 0; the LPT searches run in lock step
-        int q[LPT];  // indices into stage (kept as indices so the reads
-                     // stay LDS reads)
+        // else 0; the LPT searches run in lock step.  Positions are byte
+        // offsets from the stage (one add per probe, no scaling), and the
+        // reads stay LDS reads because every address is the stage plus an
+        // offset.
+        const char* sb = reinterpret_cast<const char*>(stage);
+        int qb[LPT];
 #pragma unroll
-        for (int l = 0; l < LPT; ++l) q[l] = i * kLdsW;
-        int len = s_width[i] - 1;
+        for (int l = 0; l < LPT; ++l) qb[l] = i * kLdsW * (int)sizeof(R);
+        int len = width - 1;
         while (len > 1) {
           const int half = len >> 1;
+          const int hb = half * (int)sizeof(R);
 #pragma unroll
-          for (int l = 0; l < LPT; ++l)
-            q[l] = (stage[q[l] + half].e <= e[l]) ? q[l] + half : q[l];
+          for (int l = 0; l < LPT; ++l) {
+            // the probe's offset is kept as is (opaque to the compiler), so
+            // the step is one add, the read, a compare and a select between
+            // two registers
+            int cand = qb[l] + hb;
+            asm volatile("" : "+v"(cand));
+            const double pe = reinterpret_cast<const R*>(sb + cand)->e;
+            qb[l] = pe <= e[l] ? cand : qb[l];
+          }
           len -= half;
         }
 #pragma unroll
         for (int l = 0; l < LPT; ++l) {
-          lo[l] = stage[q[l]];
-          hi[l] = stage[q[l] + 1];
-          pin_rec(lo[l]);
-          pin_rec(hi[l]);
+          lo[l] = *reinterpret_cast<const R*>(sb + qb[l]);
+          hi[l] = *reinterpret_cast<const R*>(sb + qb[l] + sizeof(R));
+          pin_rec(lo[l], true);
+          pin_rec(hi[l], false);
         }
       } else {
         if (!have_loc) {
@@ -925,11 +964,12 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
     int i = 0;
     if constexpr (PREC == XS_FP32) {
       for (; i + 1 < cnt; i += 2) {
-        step(i);
-        step(i + 1);
+        const int2 w2 = *reinterpret_cast<const int2*>(&s_win[i]);
+        step(i, __builtin_amdgcn_readfirstlane(w2.x));
+        step(i + 1, __builtin_amdgcn_readfirstlane(w2.y));
       }
     }
-    for (; i < cnt; ++i) step(i);
+    for (; i < cnt; ++i) step(i, __builtin_amdgcn_readfirstlane(s_win[i]));
     __syncthreads();  // the stage and window tables are rewritten next group
   }
 #pragma unroll

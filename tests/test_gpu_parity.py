@@ -551,3 +551,58 @@ def test_wave_union_search_dense_and_sparse_bins():
                 assert np.array_equal(out, want), (prec, bs)
     finally:
         h.close()
+
+
+def test_fraction_division_on_adversarial_spacings():
+    """The fraction's correctly rounded division (seeded, in the FP32 form,
+    by the reciprocal the FP32 records carry) on spacings whose mantissas
+    are all ones, exact powers of two, one ulp above them, and ratios of
+    odd integers, queried at sixteenths of every interval, at its ends and
+    their neighbours: every kernel returns the oracle's bits in both
+    forms."""
+    import synth
+    say("division on adversarial spacings")
+    steps = np.array([np.ldexp(2.0 - 2.0 ** -52, -21), 2.0 ** -20,
+                      np.ldexp(1.0 + 2.0 ** -52, -20), 3.0 * 2.0 ** -21,
+                      np.ldexp(1.0 - 2.0 ** -53, -19), 7.0 / 3.0 * 2.0 ** -20,
+                      np.ldexp(1.5, -22), np.ldexp(1.9999999999999996, -18)])
+    grids = []
+    for k, start in enumerate((1e-3, 0.25, 0.5 - 2.0 ** -30)):
+        d = np.roll(steps, k)
+        e = start + np.concatenate(([0.0], np.cumsum(np.tile(d, 150))))
+        grids.append(e)
+    offs = np.zeros(4, dtype=np.int64)
+    offs[1:] = np.cumsum([len(g) for g in grids])
+    energy = np.concatenate(grids)
+    assert all(np.all(np.diff(g) > 0) for g in grids)
+    s = synth.Stream(19, 1)
+    xsv = s.lognormal(len(energy) * 5).reshape(-1, 5)
+    t = synth.Tables(offs, energy, xsv, np.array([0, 3, 4, 6], np.int32),
+                     np.array([0, 1, 2, 1, 2, 0], np.int32),
+                     np.array([1.0, 0.5, 0.25, 1.0, 0.75, 0.125]))
+    h = xs.xs_create_tables(t, ALL_FLAGS, 1000)
+    try:
+        E = []
+        for g in grids:
+            lo, hi = g[:-1], g[1:]
+            for j in range(17):
+                E.append(lo + (hi - lo) * (j / 16.0))
+            E += [np.nextafter(lo, np.inf), np.nextafter(hi, 0)]
+        E = np.concatenate(E)
+        m = (np.arange(len(E)) % 3).astype(np.int32)
+        ref, ref32 = oracle.lookup(t, E, m), oracle.lookup_f32(t, E, m)
+        Ed, md = dev(E, torch.float64), dev(m, torch.int32)
+        shapes = [dict(sort="none", lookups_per_thread=1, unroll=1),
+                  dict(sort="band_material", sort_threshold=0, block_size=128,
+                       lookups_per_thread=1, unroll=1, lds_stage=1),
+                  dict(sort="band_material", sort_threshold=0, block_size=64,
+                       lookups_per_thread=2, unroll=1, lds_stage=3),
+                  dict(sort="none", block_size=64, lookups_per_thread=1,
+                       unroll=1, lds_stage=0, wave_per_lookup=1)]
+        for prec, want in ((xs.XS_FP64, ref), (xs.XS_FP32, ref32)):
+            for grid in ("nuclide", "hash", "unionized"):
+                for k in shapes:
+                    out = run(h, Ed, md, precision=prec, grid=grid, **k)
+                    assert np.array_equal(out, want), (prec, grid, k)
+    finally:
+        h.close()
