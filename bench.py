@@ -6,9 +6,11 @@ The workload is the full-size synthetic table set: 355 nuclides x 11,303
 grid points, 12 materials of 4 to 321 nuclides, 10,000,000 lookups with
 log-uniform energies and uniform materials (see synth.workloads).
 
-Two forms are timed: the plain FP64 lookup (per-nuclide bisection, no sort,
-256-lane blocks, one lookup per lane) and the FP32 form with parameters
-chosen by the library's tuner; `value` is the latter.  The JSON line carries
+Two forms are timed for the headline: the plain FP64 lookup (per-nuclide
+bisection, no sort, 256-lane blocks, one lookup per lane) and the FP32 form
+with parameters chosen by the library's tuner; `value` is the latter.  The
+FP64 form tuned the same way is timed beside them (`tuned_fp64`), so the
+FP32 form's gain over plain FP64 splits into method and precision.  The JSON line carries
 the dominant kernel's roofline (algorithmic flops or bytes per launch /
 average kernel time from HIP events on the launch stream, against the
 vendor peaks, with the issue ceiling and the demand and measured HBM
@@ -619,7 +621,7 @@ def tuner_study(args, torch, synth, xs):
     t0 = time.perf_counter()
     ex = xs.xs_tune_search(7, xs.xs_tune_config_default(
         precision=xs.XS_FP32, strategy=xs.XS_TUNE_EXHAUSTIVE,
-        timeout_factor=0.0, hash_bins=bins), measure)
+        timeout_factor=0.0, hash_bins=bins, confirm=0), measure)
     wall = time.perf_counter() - t0
     opt = ex.best_ms
     log(f"exhaustive: {ex.space_size} configurations in {wall:.1f} s, "
@@ -644,7 +646,7 @@ def tuner_study(args, torch, synth, xs):
             return v
         r = xs.xs_tune_search(7, xs.xs_tune_config_default(
             precision=xs.XS_FP32, strategy=xs.XS_TUNE_FOREST,
-            max_evals=evals, seed=seed, hash_bins=bins), rec)
+            max_evals=evals, seed=seed, hash_bins=bins, confirm=0), rec)
         run_best = np.minimum.accumulate(trace)
         hit = np.nonzero(run_best <= 1.05 * opt)[0]
         forest.append((r.best_ms / opt, int(hit[0]) + 1 if len(hit) else None))
@@ -652,7 +654,7 @@ def tuner_study(args, torch, synth, xs):
     allc = []
     xs.xs_tune_search(7, xs.xs_tune_config_default(
         precision=xs.XS_FP32, strategy=xs.XS_TUNE_EXHAUSTIVE,
-        timeout_factor=0.0, hash_bins=bins),
+        timeout_factor=0.0, hash_bins=bins, confirm=0),
         lambda p, cutoff: allc.append(replay(p, cutoff)) or allc[-1])
     allv = np.array(allc)
     costs = np.sort(allv)
@@ -1044,6 +1046,23 @@ def main(argv=None):
         log(f"FP32 tuned: {tuned['value']:.4g} lookups/s, "
             f"{tuned['ms_per_step']:.3f} ms/step")
 
+    # The FP64 form tuned the same way: what the sort, the union index and
+    # LDS staging give without the narrower data, so the FP32 form's gain
+    # over plain FP64 splits into method and precision.
+    tuned64 = out_tuned64 = None
+    if args.only is None and not args.params:
+        cfg = xs.xs_tune_config_default(precision=xs.XS_FP64,
+                                        max_evals=args.tune_evals, reps=3,
+                                        warmup=1)
+        log("tuning the FP64 form")
+        r = xs.xs_tune(h, E, m, cfg)
+        p64 = xs.xs_resolve_params(h, n, xs.xs_params_default(xs.XS_FP64))
+        tuned64, out_tuned64 = measure(p64)
+        tuned64["tuner"] = {k: v for k, v in r.as_dict().items()
+                            if k not in ("best", "baseline")}
+        log(f"FP64 tuned: {tuned64['value']:.4g} lookups/s, "
+            f"{tuned64['ms_per_step']:.3f} ms/step")
+
     head = tuned or plain
     cpu = None
     ref64 = None
@@ -1068,6 +1087,8 @@ def main(argv=None):
         if out_tuned is not None:
             ref32 = oracle.lookup_f32(t, q.E, q.mat, threads=threads)
             parity["tuned_fp32"] = parity_fp32(out_tuned, ref32, ref64)
+        if out_tuned64 is not None:
+            parity["tuned_fp64"] = parity_fp64(out_tuned64, ref64)
         for k, v in parity.items():
             log(f"parity {k}: ok={v['ok']} max rel per channel "
                 + " ".join(f"{x:.3g}" for x in v["max_rel"]))
@@ -1117,9 +1138,14 @@ def main(argv=None):
         "parity": parity,
         "plain_fp64": plain,
         "tuned_fp32": tuned,
+        "tuned_fp64": tuned64,
     }
     if plain and tuned:
         line["fp32_tuned_over_fp64_plain"] = tuned["value"] / plain["value"]
+    if tuned64 and tuned:
+        line["fp32_tuned_over_fp64_tuned"] = tuned["value"] / tuned64["value"]
+    if tuned64 and plain:
+        line["fp64_tuned_over_fp64_plain"] = tuned64["value"] / plain["value"]
     if extras is not None:
         line["extras"] = extras
     print(json.dumps(line), flush=True)

@@ -361,6 +361,15 @@ typedef struct {
                              (0: one grid, hash_bins 0); xs_tune offers
                              every hash grid of the handle */
   int32_t hash_bins[XS_MAX_HASH_GRIDS];
+  int32_t confirm;        /* finalists re-timed after the search (< 2: none).
+                             The search scores each configuration on one
+                             evaluation, so among near-equal configurations
+                             the winner is often the one that drew the
+                             luckier run.  The `confirm` best configurations
+                             and the baseline are evaluated again, round-
+                             robin, three times, and the lowest median wins;
+                             best_ms and baseline_ms are then those medians.
+                             These runs are not counted in `evaluated`. */
 } xs_tune_config;
 
 typedef struct {
@@ -390,7 +399,7 @@ typedef xs_status (*xs_eval_fn)(const xs_params* p, double cutoff_ms,
 
 /* Fills *c with the defaults: FOREST, 48 evaluations, 10 initial samples,
  * batch 1, best of 5 after 1 warm-up, time-out 1.5x baseline, kappa 1.96,
- * seed 1234, all grids and sorts, xs_lookup_batch. */
+ * seed 1234, all grids and sorts, xs_lookup_batch, 3 finalists confirmed. */
 xs_status xs_tune_config_default(xs_tune_config* c);
 
 /* Searches the space above over the grid methods in built_grids & grid_mask

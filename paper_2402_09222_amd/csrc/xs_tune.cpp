@@ -19,7 +19,8 @@
 // flight, LDS staging, wave per lookup) (x queue mode), with invalid
 // combinations removed.  Configurations that launch the same kernels at the
 // tuned batch size (a threshold on either side of n, a queue mode behind a
-// sort) share one device measurement.  Winners go into the handle per
+// sort) share one device measurement.  The best few are timed again,
+// interleaved, before the winner is chosen.  Winners go into the handle per
 // batch-size class and, with a cache path, into a text file keyed by device,
 // table checksum, precision, entry point and class (the paper's performance
 // database, section 3), from which later runs resolve without tuning.
@@ -383,14 +384,19 @@ xs_status xs_tune_config_default(xs_tune_config* c) {
   c->seed = 1234;
   c->grid_mask = 0;
   c->sort_mask = 0;
+  c->confirm = 3;
   return XS_OK;
 }
 
 // The search; `baseline`, when given, is the configuration evaluated first
 // (the time-out reference, and what the result can never be worse than).
+// `round`, when given, is told the confirmation round before its runs (0, 1,
+// ...) and -1 after the last, so an evaluator that reuses measurements can
+// take fresh ones there.
 static xs_status tune_search(uint32_t built_grids, const xs_tune_config* cfg,
                              xs_eval_fn eval, void* user,
                              const xs_params* baseline,
+                             void (*round)(void* user, int r),
                              xs_tune_result* result) {
   clear_error();
   if (!cfg || !eval || !result)
@@ -403,6 +409,8 @@ static xs_status tune_search(uint32_t built_grids, const xs_tune_config* cfg,
   if (cfg->active != 0 && cfg->active != 1)
     return fail(XS_EINVAL, "active must be 0 or 1");
   if (cfg->batch < 0) return fail(XS_EINVAL, "batch must be >= 0");
+  if (cfg->confirm < 0 || cfg->confirm > 64)
+    return fail(XS_EINVAL, "confirm must be in [0, 64]");
   if (cfg->grid_mask & ~7u) return fail(XS_EINVAL, "unknown grid mask bits");
   if (cfg->sort_mask & ~31u) return fail(XS_EINVAL, "unknown sort mask bits");
   if (cfg->n_hash_grids < 0 || cfg->n_hash_grids > XS_MAX_HASH_GRIDS)
@@ -522,22 +530,67 @@ static xs_status tune_search(uint32_t built_grids, const xs_tune_config* cfg,
         if (xs_status st = S.run_one(acq[k].second)) return st;
     }
   }
+  int win = S.best;
+  double win_ms = std::exp(S.obj[S.best]);
+  double base_ms = std::exp(S.obj[b0]);
+  if (cfg->confirm >= 2 && S.order.size() >= 2) {
+    // The finalists: the best `confirm` configurations by their search
+    // score, then the baseline if it is not among them.  Each round times
+    // every finalist once, starting one further along the list each round,
+    // so slow drifts of clock or temperature fall on all of them alike; a
+    // finalist's score is the median of its rounds (its search run, picked
+    // for being low, is left out).  Ties keep the better-ranked finalist.
+    constexpr int kRounds = 3;
+    std::vector<int> fin = S.order;
+    std::stable_sort(fin.begin(), fin.end(),
+                     [&](int a, int b) { return S.obj[a] < S.obj[b]; });
+    fin.resize(std::min<size_t>(fin.size(), (size_t)cfg->confirm));
+    if (std::find(fin.begin(), fin.end(), b0) == fin.end()) fin.push_back(b0);
+    const size_t F = fin.size();
+    std::vector<std::vector<double>> t(F);
+    for (int k = 0; k < kRounds; ++k) {
+      if (round) round(user, k);
+      for (size_t j = 0; j < F; ++j) {
+        const size_t f = (j + (size_t)k) % F;
+        double ms = 0;
+        if (xs_status st = eval(&S.space[fin[f]].p, S.cutoff, &ms, user)) {
+          if (round) round(user, -1);
+          return st;
+        }
+        if (!(ms > 0) || !std::isfinite(ms) || ms > S.cutoff) ms = S.cutoff;
+        t[f].push_back(ms);
+      }
+    }
+    if (round) round(user, -1);
+    std::vector<double> med(F);
+    for (size_t f = 0; f < F; ++f) {
+      std::sort(t[f].begin(), t[f].end());
+      med[f] = t[f][kRounds / 2];
+    }
+    size_t w = 0;
+    for (size_t f = 1; f < F; ++f)
+      if (med[f] < med[w]) w = f;
+    win = fin[w];
+    win_ms = med[w];
+    base_ms = med[std::find(fin.begin(), fin.end(), b0) - fin.begin()];
+  }
   xs_tune_result r{};
-  r.best = S.space[S.best].p;
-  r.best_ms = std::exp(S.obj[S.best]);
+  r.best = S.space[win].p;
+  r.best_ms = win_ms;
   r.baseline = S.space[b0].p;
-  r.baseline_ms = std::exp(S.obj[b0]);
+  r.baseline_ms = base_ms;
   r.evaluated = (int)S.order.size();
   r.cut = S.cut;
   r.space_size = N;
-  r.best_eval = S.best_eval;
+  r.best_eval =
+      (int)(std::find(S.order.begin(), S.order.end(), win) - S.order.begin()) + 1;
   *result = r;
   return XS_OK;
 }
 
 xs_status xs_tune_search(uint32_t built_grids, const xs_tune_config* cfg,
                          xs_eval_fn eval, void* user, xs_tune_result* result) {
-  return tune_search(built_grids, cfg, eval, user, nullptr, result);
+  return tune_search(built_grids, cfg, eval, user, nullptr, nullptr, result);
 }
 
 }  // extern "C"
@@ -549,7 +602,7 @@ namespace {
 // caller's stream: `warmup` untimed runs, then up to `reps` timed runs (best
 // kept); stops after the first timed run when it already exceeds the
 // cut-off.  Configurations that launch the same kernels at this n share one
-// measurement.
+// measurement (within the search, and within each confirmation round).
 struct DeviceEval {
   xs_tables_t h;
   int64_t n;
@@ -564,6 +617,7 @@ struct DeviceEval {
   hipEvent_t a, b;
   std::map<std::vector<int64_t>, double> memo;
   int measured = 0;
+  int round = -1;  // confirmation round, -1 during the search
 
   // What decides the kernels a call runs at this n.
   std::vector<int64_t> launch_key(const xs_params& p) const {
@@ -581,10 +635,13 @@ struct DeviceEval {
   }
 };
 
+void device_round(void* user, int r) { ((DeviceEval*)user)->round = r; }
+
 int32_t device_eval(const xs_params* p, double cutoff_ms, double* ms,
                     void* user) {
   DeviceEval& d = *(DeviceEval*)user;
-  const std::vector<int64_t> key = d.launch_key(*p);
+  std::vector<int64_t> key = d.launch_key(*p);
+  key.push_back(d.round);  // each confirmation round measures afresh
   auto it = d.memo.find(key);
   if (it != d.memo.end()) {
     *ms = it->second;
@@ -603,7 +660,7 @@ int32_t device_eval(const xs_params* p, double cutoff_ms, double* ms,
     best = std::min(best, (double)t);
     if (best > cutoff_ms) break;
   }
-  ++d.measured;
+  if (d.round < 0) ++d.measured;
   d.memo[key] = best;
   *ms = best;
   return XS_OK;
@@ -863,7 +920,7 @@ xs_status xs_tune(xs_tables_t h, const xs_tune_request* req,
   DeviceEval d{h, 0, req->d_E, req->d_mat, req->d_active, req->d_out,
                req->d_ws, req->ws_bytes, (hipStream_t)req->stream,
                std::max(0, cfg.warmup), std::max(1, cfg.reps), nullptr,
-               nullptr, {}, 0};
+               nullptr, {}, 0, -1};
   XS_HIP(hipEventCreate(&d.a));
   XS_HIP(hipEventCreate(&d.b));
   xs_status st = XS_OK;
@@ -894,7 +951,9 @@ xs_status xs_tune(xs_tables_t h, const xs_tune_request* req,
       d.n = n;
       d.memo.clear();
       d.measured = 0;
-      if ((st = tune_search(built, &cfg, device_eval, &d, &def, &r))) break;
+      if ((st = tune_search(built, &cfg, device_eval, &d, &def, device_round,
+                            &r)))
+        break;
       r.measured = d.measured;
       fresh.push_back(CacheEntry{key, r.best, r.best_ms});
     }

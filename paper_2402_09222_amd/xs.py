@@ -157,6 +157,7 @@ class xs_tune_config(ctypes.Structure):
         ("sort_mask", ctypes.c_uint32),
         ("n_hash_grids", ctypes.c_int32),
         ("hash_bins", ctypes.c_int32 * XS_MAX_HASH_GRIDS),
+        ("confirm", ctypes.c_int32),
     ]
 
 

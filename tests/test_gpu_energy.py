@@ -67,7 +67,7 @@ def test_tune_for_energy_and_edp(env, objective):
 
     cfg = xs.xs_tune_config_default(precision=xs.XS_FP32, max_evals=5,
                                     init_samples=4, seed=3, timeout_factor=0.0,
-                                    grid_mask=4, sort_mask=1 | 16)
+                                    grid_mask=4, sort_mask=1 | 16, confirm=0)
     r = xs.xs_tune_search(7, cfg, evaluate)
     say("winner", r.best.as_dict(), r.best_ms, "baseline", r.baseline_ms)
     assert r.evaluated == len(seen) == 5

@@ -90,7 +90,7 @@ def key_of(c):
 def test_exhaustive_finds_optimum():
     rec = Recorder()
     cfg = xs.xs_tune_config_default(strategy=xs.XS_TUNE_EXHAUSTIVE,
-                                    timeout_factor=0.0)
+                                    timeout_factor=0.0, confirm=0)
     r = xs.xs_tune_search(7, cfg, rec)
     assert r.evaluated == r.space_size == len(rec.calls)
     all_valid(rec.calls)
@@ -147,7 +147,8 @@ def test_conditional_parameters_never_vary_outside_their_condition():
     for active in (0, 1):
         rec = Recorder()
         cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=0.0,
-                                        active=active, hash_bins=bins)
+                                        active=active, hash_bins=bins,
+                                        confirm=0)
         r = xs.xs_tune_search(7, cfg, rec)
         assert r.evaluated == len(rec.calls) == r.space_size
         all_valid(rec.calls, hash_bins=bins, active=bool(active))
@@ -189,7 +190,8 @@ def test_forest_tunes_the_papers_parameters():
     bins = [4000, 8192, 32768]
     allc = Recorder(paper_cost)
     ex = xs.xs_tune_search(7, xs.xs_tune_config_default(
-        strategy=0, timeout_factor=0.0, active=1, hash_bins=bins), allc)
+        strategy=0, timeout_factor=0.0, active=1, hash_bins=bins, confirm=0),
+        allc)
     opt = ex.best_ms
     assert ex.space_size == 9620
     assert ex.best.grid == 1 and ex.best.hash_bins == 8192
@@ -219,7 +221,7 @@ def test_timeout_rule_cuts_and_scores_at_cutoff():
     """Baseline first; every later configuration slower than 1.5x the
     baseline is cut and recorded at exactly the time-out value."""
     rec = Recorder()
-    cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=1.5)
+    cfg = xs.xs_tune_config_default(strategy=0, timeout_factor=1.5, confirm=0)
     r = xs.xs_tune_search(7, cfg, rec)
     base = rec.calls[0]
     assert (base["grid"], base["sort"], base["bs"], base["lpt"], base["u"],
@@ -242,7 +244,7 @@ def test_forest_beats_random_search():
     for seed in range(8):
         cfg = xs.xs_tune_config_default(strategy=xs.XS_TUNE_FOREST,
                                         max_evals=40, seed=seed,
-                                        timeout_factor=0.0)
+                                        timeout_factor=0.0, confirm=0)
         rec = Recorder()
         r = xs.xs_tune_search(7, cfg, rec)
         assert r.evaluated == 40 == len(rec.calls)
@@ -256,7 +258,7 @@ def test_forest_beats_random_search():
         rng = np.random.default_rng(seed)
         allc = Recorder()
         xs.xs_tune_search(7, xs.xs_tune_config_default(
-            strategy=0, timeout_factor=0.0), allc)
+            strategy=0, timeout_factor=0.0, confirm=0), allc)
         costs = np.array([cost_of(c) for c in allc.calls])
         rand.append(costs[rng.choice(space, 40, replace=False)].min())
     assert max(forest) <= 1.5 * opt
@@ -303,3 +305,69 @@ def test_errors():
         with pytest.raises(xs.XsError) as e:
             xs.xs_tune_search(7, xs.xs_tune_config_default(**bad), Recorder())
         assert e.value.status == xs.XS_EINVAL, bad
+
+
+def pkey(p):
+    return (p.grid, p.sort, p.block_size, p.lookups_per_thread, p.unroll,
+            p.lds_stage, p.wave_per_lookup, p.hash_bins, p.sort_threshold,
+            p.queue)
+
+
+def test_confirmation_retimes_the_finalists():
+    """The search scores each configuration on one run, so a lucky draw can
+    make a slower configuration look best.  With confirm = 3 the best three
+    by that score and the baseline are timed again, three rounds, each
+    starting one finalist further along, and the lowest median wins; those
+    runs are not counted as evaluations."""
+    opts = dict(strategy=0, timeout_factor=0.0, grid_mask=4, sort_mask=16)
+    keys = []
+    ex = xs.xs_tune_search(7, xs.xs_tune_config_default(confirm=0, **opts),
+                           lambda p, cut: keys.append(pkey(p)) or 1.0)
+    # distinct true times: cost() with ties broken by enumeration order
+    rank = {k: i for i, k in enumerate(keys)}
+
+    def true_ms(p):
+        return cost(p) * (1.0 + 1e-3 * rank[pkey(p)])
+
+    times = {}
+    xs.xs_tune_search(7, xs.xs_tune_config_default(confirm=0, **opts),
+                      lambda p, cut: times.setdefault(pkey(p), true_ms(p)))
+    ranked = sorted(times.items(), key=lambda kv: kv[1])
+    (k1, t1), (k2, t2) = ranked[0], ranked[1]
+    assert t1 < t2 < 1.05 * t1
+    first = {k1: 1.05, k2: 0.9}  # k1 unlucky, k2 lucky on their search runs
+
+    def noisy():
+        calls = []
+
+        def ev(p, cut):
+            k = pkey(p)
+            calls.append(k)
+            return true_ms(p) * (first.get(k, 1.0) if calls.count(k) == 1
+                                 else 1.0)
+        return calls, ev
+
+    plain, ev = noisy()
+    r0 = xs.xs_tune_search(7, xs.xs_tune_config_default(confirm=0, **opts), ev)
+    assert pkey(r0.best) == k2 and r0.best_ms == pytest.approx(0.9 * t2)
+    assert r0.evaluated == len(plain) == ex.space_size
+
+    calls, ev = noisy()
+    r = xs.xs_tune_search(7, xs.xs_tune_config_default(confirm=3, **opts), ev)
+    assert r.evaluated == ex.space_size
+    search, extra = calls[:r.evaluated], calls[r.evaluated:]
+    scores = {k: times[k] * first.get(k, 1.0) for k in search}
+    top3 = sorted(scores, key=scores.get)[:3]
+    assert top3[0] == k2 and k1 in top3
+    base = search[0]
+    fin = top3 + ([base] if base not in top3 else [])
+    F = len(fin)
+    assert extra == [fin[(j + k) % F] for k in range(3) for j in range(F)]
+    assert pkey(r.best) == k1 and r.best_ms == pytest.approx(t1)
+    assert pkey(r.baseline) == base
+    assert r.baseline_ms == pytest.approx(times[base])
+    assert r.best_ms <= r.baseline_ms
+    assert search[r.best_eval - 1] == k1
+    with pytest.raises(xs.XsError):
+        xs.xs_tune_search(7, xs.xs_tune_config_default(confirm=-1, **opts),
+                          lambda p, cut: 1.0)
