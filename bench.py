@@ -20,9 +20,9 @@ timed outputs with the oracle on every lookup of the batch; the run exits
 with status 1 if either differs beyond its bar.  After the timed steps (and
 outside `value`), `extras` carries the particles-in-flight sweep (1e5 to
 8e6 lookups, the FP32 form tuned per size over the launch shapes and the
-paper's tunables) and the uneven request stream (the persistent
-graph-launched kernel against per-request launches, p50/p99 latency) in
-brief, each checked against the oracle on samples (--no-extras skips them).
+paper's tunables) and the uneven request stream (the graph-launched
+request stream in both modes against per-request launches, p50/p99 latency)
+in brief, each checked against the oracle on samples (--no-extras skips them).
 """
 from __future__ import annotations
 
@@ -424,8 +424,9 @@ def sweep_in_flight(args, torch, synth, xs):
 def request_stream(args, torch, synth, xs):
     """Config 5: an uneven stream of requests (sizes log-uniform in
     [1e3, 1e6], energies 70 % log-uniform and 30 % from narrow peaks) served
-    by the persistent graph-launched kernel (xs_stream_*, one graph launch
-    for the whole batch), by one xs_lookup_requests call (batch-sorted: one
+    by a request stream (xs_stream_*, one graph launch for the whole batch:
+    the sorted pipeline captured into the graph, and the persistent kernel
+    over LDS-sorted tiles), by one xs_lookup_requests call (batch-sorted: one
     gathered, sorted queue; tile-sorted: one launch, tiles sorted in LDS),
     and by one xs_lookup_batch launch per request with parameters tuned per
     size class.  A request's latency in the one-launch forms runs from its
@@ -529,25 +530,37 @@ def request_stream_line(args, torch, synth, xs, h, t, n_requests,
     res_tile = one_call(p_tile)
     same["one_call_tile_sorted"] = bool(np.array_equal(snapshot(), out_launch))
 
-    # The persistent kernel: one graph launch per batch of requests.
-    stream = xs.xs_stream_create(h, p_auto, max_requests=len(reqs))
-    p_stream = xs.xs_stream_params(stream)
-    out.fill_(-1.0)
-    res_stream = None
-    for rep in range(max(1, args.steps // 5) + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xs.xs_stream_submit(stream, reqs)
-        stats, makespan = xs.xs_stream_wait(stream)
-        wall = time.perf_counter() - t0
-        lat = [r["latency_us"] for r in stats]
-        if rep > 0 and (res_stream is None or wall < res_stream["wall_s"]):
-            res_stream = {"wall_s": wall, "lookups_per_s": total / wall,
-                          "device_makespan_us": makespan,
-                          "device_lookups_per_s": total / (makespan * 1e-6),
-                          "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
-    same["persistent_stream"] = bool(np.array_equal(snapshot(), out_launch))
-    stream.close()
+    # Request streams: one graph launch per batch of requests, with the
+    # automatic parameters (the batch sorts: gather, sort, lookup and
+    # scatter captured into the stream's graph) and without a sort (the
+    # persistent kernel over LDS-sorted tiles).
+    def run_stream(params):
+        stream = xs.xs_stream_create(h, params, max_requests=len(reqs))
+        out.fill_(-1.0)
+        res = None
+        for rep in range(max(1, args.steps // 5) + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            xs.xs_stream_submit(stream, reqs)
+            stats, makespan = xs.xs_stream_wait(stream)
+            wall = time.perf_counter() - t0
+            lat = [r["latency_us"] for r in stats]
+            if rep > 0 and (res is None or wall < res["wall_s"]):
+                res = {"wall_s": wall, "lookups_per_s": total / wall,
+                       "device_makespan_us": makespan,
+                       "device_lookups_per_s": total / (makespan * 1e-6),
+                       "p50_us": _pctl(lat, 0.5), "p99_us": _pctl(lat, 0.99)}
+        p_stream = xs.xs_stream_params(stream)
+        stream.close()
+        return res, p_stream
+
+    res_stream, _ = run_stream(p_auto)
+    same["graph_stream_sorted"] = bool(np.array_equal(snapshot(), out_launch))
+    p_unsorted = xs.xs_params_default(xs.XS_FP32)
+    p_unsorted.sort = xs.XS_SORT_NONE
+    res_persist, p_stream = run_stream(p_unsorted)
+    same["graph_stream_persistent"] = bool(np.array_equal(snapshot(),
+                                                          out_launch))
 
     # The per-request launches against the oracle's FP32 form on a sample.
     import oracle
@@ -558,12 +571,13 @@ def request_stream_line(args, torch, synth, xs, h, t, n_requests,
     oracle_ok = bool(np.array_equal(out_launch[pick], ref32))
     line = {"config": "uneven request stream", "requests": len(reqs),
             "lookups": total, "per_request_launches": best_launch,
-            "persistent_stream": res_stream,
+            "graph_stream_sorted": res_stream,
+            "graph_stream_persistent": res_persist,
             "one_call_batch_sorted": res_batch,
             "one_call_tile_sorted": res_tile,
             "batch_params": p_batch.as_dict(),
             "tile_params": p_tile.as_dict(),
-            "stream_params": p_stream.as_dict(),
+            "persistent_params": p_stream.as_dict(),
             "bit_identical_to_per_request_launches": same,
             "per_request_launches_equal_oracle_on_sample": oracle_ok}
     return line, bool(oracle_ok and all(same.values()))

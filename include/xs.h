@@ -487,18 +487,29 @@ xs_status xs_tune_key_of(xs_tables_t tables, int32_t precision,
 
 /* ---- request streams ------------------------------------------------------ */
 
-/* Many uneven batches served by one persistent kernel launched from a HIP
- * graph (paper section 5.1: the particle buffer is refilled after each
- * kernel call, and with short kernels launches and queue-count transfers to
- * the host leave bubbles).  The graph [reset times] -> [persistent kernel]
- * is built once; before each launch its kernel arguments (request and tile
- * counts, the batch's tag, the largest request size) are rewritten.  The
- * kernel's fixed grid strides over the batch's 1024-lookup tiles, so no loop
- * bound comes from device memory; each block checks the tile's descriptor
- * (the batch's tag, a size within the host's bound, the tile inside the
- * request), sorts the tile in LDS by material and energy, looks it up, and
- * stamps the request's first and last tile with the device wall clock.
- * Results equal xs_lookup_batch's bit for bit. */
+/* Many uneven batches, each served by one launch of a HIP graph (paper
+ * section 5.1: the particle buffer is refilled after each kernel call, and
+ * with short kernels launches and queue-count transfers to the host leave
+ * bubbles).  The stream's parameters are resolved for each batch's total
+ * size, and they pick one of two graphs:
+ *  - sorted (the resolved sort != XS_SORT_NONE and total >= sort_threshold,
+ *    total < 2^31, debug mode off): the batch-sorted pipeline of
+ *    xs_lookup_requests (gather every request into one queue, sort it, look
+ *    it up with the resolved launch shape, scatter the results back) is
+ *    captured for the batch and updates one instantiated graph in place; a
+ *    request's time runs from the first gathered tile to its last scattered
+ *    tile, so every request finishes with the batch;
+ *  - otherwise the persistent kernel: the graph [reset times] ->
+ *    [persistent kernel] is built once, and before each launch its kernel
+ *    arguments (request and tile counts, the batch's tag, the largest
+ *    request size) are rewritten.  The kernel's fixed grid strides over the
+ *    batch's 1024-lookup tiles, so no loop bound comes from device memory;
+ *    each block checks the tile's descriptor (the batch's tag, a size within
+ *    the host's bound, the tile inside the request), sorts the tile in LDS by
+ *    material and energy, looks it up, and stamps the request's first and
+ *    last tile with the device wall clock.  Requests finish as their tiles
+ *    do, at the throughput of unsorted lookups.
+ * Results equal xs_lookup_batch's bit for bit in both. */
 typedef struct xs_stream_s* xs_stream_t;
 
 typedef struct {
@@ -517,9 +528,13 @@ typedef struct {
 
 /* Creates a stream for batches of up to max_requests requests on `stream`
  * (a hipStream_t as void*).  params (NULL: all automatic, FP64) fixes the
- * precision, grid method and nuclides in flight; sort, block size, lookups
- * per lane and threshold do not apply.  Builds and instantiates the graph
- * once (allocates; the other stream calls do not). */
+ * precision; its other fields are resolved for each batch's total (XS_AUTO
+ * fields from the handle's tuned parameters, as xs_lookup_batch would), and
+ * the persistent kernel takes the grid method and nuclides in flight
+ * resolved here for a batch of 2^20 lookups.  Builds and instantiates the
+ * persistent kernel's graph once (allocates); a sorted batch larger than
+ * any before also allocates, on submit, its queue, results and sort
+ * workspace (kept until the stream is destroyed). */
 xs_status xs_stream_create(xs_tables_t tables, const xs_params* params,
                            int32_t max_requests, void* stream,
                            xs_stream_t* out);
@@ -527,9 +542,9 @@ xs_status xs_stream_create(xs_tables_t tables, const xs_params* params,
 /* Enqueues one batch (HOST array of count descriptors, read during the call)
  * on the stream: the descriptors are copied to the device on the stream
  * object's own upload stream and the host waits for that copy (no wait on
- * the caller's stream), then the graph is launched on the caller's stream.
- * One batch may be in flight per stream object; XS_EINVAL if the previous
- * one was not waited for. */
+ * the caller's stream), then the batch's graph is launched on the caller's
+ * stream.  One batch may be in flight per stream object; XS_EINVAL if the
+ * previous one was not waited for. */
 xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
                            int32_t count);
 
@@ -540,7 +555,7 @@ xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
 xs_status xs_stream_wait(xs_stream_t s, xs_request_stats* stats,
                          double* makespan_us);
 
-/* The resolved parameters the stream runs with. */
+/* The parameters the persistent kernel runs with (resolved at creation). */
 xs_status xs_stream_params(xs_stream_t s, xs_params* out);
 
 /* Waits for any batch in flight and frees the stream.  NULL is a no-op. */

@@ -298,6 +298,30 @@ void energy_key_shift(const xs_tables_s* h, int64_t* bmin, int* shift) {
   *shift = sh;
 }
 
+// Batch-sorted serving (after the stamps are reset): one gather kernel
+// copies every request into one queue, the queue is sorted and looked up as
+// one batch, and one scatter kernel writes each request's results back.
+// `lookup` runs the sorted lookup of the gathered queue on the stream.
+template <class Lookup>
+xs_status enqueue_batch_sorted(const ReqDev* reqs_dev, int count, int64_t tiles,
+                               int precision, unsigned long long* stamps,
+                               double* E_all, int32_t* m_all, void* out_all,
+                               hipStream_t s, Lookup lookup) {
+  const dim3 grid((unsigned)tiles), block(kStreamThreads);
+  hipLaunchKernelGGL(k_requests_gather, grid, block, 0, s, reqs_dev, count,
+                     E_all, m_all, stamps);
+  XS_HIP(hipGetLastError());
+  if (xs_status st = lookup()) return st;
+  if (precision == XS_FP64)
+    hipLaunchKernelGGL(k_requests_scatter<double>, grid, block, 0, s, reqs_dev,
+                       count, (const double*)out_all, stamps);
+  else
+    hipLaunchKernelGGL(k_requests_scatter<float>, grid, block, 0, s, reqs_dev,
+                       count, (const float*)out_all, stamps);
+  XS_HIP(hipGetLastError());
+  return XS_OK;
+}
+
 // Validation, parameters and workspace layout of one xs_lookup_requests call.
 struct RequestPlan {
   xs_params p{};
@@ -417,29 +441,18 @@ xs_status xs_lookup_requests(xs_tables_t h, const xs_request* reqs,
   XS_HIP(hipGetLastError());
   if (plan.tiles == 0) return XS_OK;
   const xs_params& p = plan.p;
-  const dim3 grid((unsigned)plan.tiles), block(kStreamThreads);
 
   if (plan.batch_sorted) {
-    // Gather every request into one queue, sort and look it up as one
-    // batch, and scatter the results back per request.
     auto* E_all = (double*)(ws + plan.off_E);
     auto* m_all = (int32_t*)(ws + plan.off_mat);
     void* out_all = ws + plan.off_out;
-    hipLaunchKernelGGL(k_requests_gather, grid, block, 0, s, reqs_dev, count,
-                       E_all, m_all, stamps);
-    XS_HIP(hipGetLastError());
-    if (xs_status st = xs_lookup_batch(h, plan.total, E_all, m_all, out_all,
-                                       &p, ws + plan.off_lookup_ws,
-                                       plan.lookup_ws_bytes, stream))
-      return st;
-    if (p.precision == XS_FP64)
-      hipLaunchKernelGGL(k_requests_scatter<double>, grid, block, 0, s,
-                         reqs_dev, count, (const double*)out_all, stamps);
-    else
-      hipLaunchKernelGGL(k_requests_scatter<float>, grid, block, 0, s,
-                         reqs_dev, count, (const float*)out_all, stamps);
-    XS_HIP(hipGetLastError());
-    return XS_OK;
+    return enqueue_batch_sorted(
+        reqs_dev, count, plan.tiles, p.precision, stamps, E_all, m_all,
+        out_all, s, [&] {
+          return xs_lookup_batch(h, plan.total, E_all, m_all, out_all, &p,
+                                 ws + plan.off_lookup_ws, plan.lookup_ws_bytes,
+                                 stream);
+        });
   }
 
   int64_t bmin;
@@ -502,21 +515,37 @@ xs_status xs_requests_stats(const void* d_ws, int32_t count, void* stream,
 
 }  // extern "C"
 
-// ---- request streams: the persistent kernel in a reusable graph ------------
+// ---- request streams: a reusable graph per batch ----------------------------
+//
+// Two modes, chosen per batch from the parameters resolved for its total
+// size.  Tile mode (no sort, or fewer lookups than the sort threshold): the
+// graph [reset stamps] -> [persistent kernel], built once; each submit
+// rewrites the two nodes' arguments.  Sorted mode: the batch-sorted
+// pipeline of xs_lookup_requests (gather, sort, staged lookup, scatter) is
+// captured from a private stream and the stream's second executable graph
+// is updated in place (re-instantiated only when the kernels differ from
+// the previous sorted batch's); its buffers grow with the largest batch.
 //
 // Ordering of a submit: the descriptors are written to pinned host memory,
 // copied to the device on the stream object's own upload stream, and the
-// host waits for that copy to complete before it rewrites the graph's
-// kernel arguments and launches the graph on the caller's stream.  The
-// kernel therefore never starts before its descriptors are in device
-// memory, whatever the runtime does to order a copy against a graph launch
-// on one stream; and each descriptor carries the batch's tag, which the
-// kernel checks before it uses the descriptor.
+// host waits for that copy to complete before it rewrites or captures the
+// graph and launches it on the caller's stream.  No kernel therefore starts
+// before its descriptors are in device memory, whatever the runtime does to
+// order a copy against a graph launch on one stream; and in tile mode each
+// descriptor carries the batch's tag, which the kernel checks before it
+// uses the descriptor.
 
 struct xs_stream_s {
   xs_tables_t tables = nullptr;
   xs_params params{};
-  hipStream_t user = nullptr;
+  xs_params user{};        // as given at creation (resolved per batch)
+  bool has_user = false;
+  hipStream_t capture = nullptr;   // sorted mode: captures the pipeline
+  hipGraphExec_t sexec = nullptr;  // sorted mode: the pipeline's graph
+  void* sorted_ws = nullptr;       // queue, results and sort workspace
+  size_t sorted_ws_bytes = 0;
+  bool last_sorted = false;        // mode of the batch in flight
+  hipStream_t stream = nullptr;  // the caller's stream (graph launches)
   hipStream_t upload = nullptr;  // descriptor copies (host waits for them)
   int32_t max_requests = 0;
   int32_t pending = 0;  // requests of the batch in flight (0 = idle)
@@ -550,6 +579,9 @@ namespace xs {
 namespace {
 
 void stream_release(xs_stream_s* s) {
+  if (s->sexec) (void)hipGraphExecDestroy(s->sexec);
+  if (s->capture) (void)hipStreamDestroy(s->capture);
+  if (s->sorted_ws) (void)hipFree(s->sorted_ws);
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->done) (void)hipEventDestroy(s->done);
@@ -605,6 +637,69 @@ hipKernelNodeParams run_params(xs_stream_s* s) {
   return kp;
 }
 
+// Captures the batch-sorted pipeline for `count` requests (descriptors
+// already in device memory) and launches it on the caller's stream.
+xs_status submit_sorted(xs_stream_s* s, int count, int64_t tiles,
+                        int64_t total, const xs_params& ps) {
+  xs_tables_t h = s->tables;
+  const size_t esz = ps.precision == XS_FP64 ? 8 : 4;
+  size_t lws = 0;
+  if (xs_status st = xs_workspace_size(h, total, &ps, &lws)) return st;
+  const size_t off_mat = align256b(8 * (size_t)total);
+  const size_t off_out = off_mat + align256b(4 * (size_t)total);
+  const size_t off_ws = off_out + align256b(esz * XS_CHANNELS * (size_t)total);
+  const size_t need = off_ws + align256b(lws);
+  if (need > s->sorted_ws_bytes) {
+    // No batch is in flight (a submit needs the previous one waited for).
+    if (s->sorted_ws) XS_HIP(hipFree(s->sorted_ws));
+    s->sorted_ws = nullptr;
+    s->sorted_ws_bytes = 0;
+    XS_HIP(hipMalloc(&s->sorted_ws, need));
+    s->sorted_ws_bytes = need;
+  }
+  char* ws = (char*)s->sorted_ws;
+  auto* E_all = (double*)ws;
+  auto* m_all = (int32_t*)(ws + off_mat);
+  void* out_all = ws + off_out;
+  hipStream_t cap = s->capture;
+  XS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  hipLaunchKernelGGL(k_requests_init, dim3((count + 1 + 255) / 256), dim3(256),
+                     0, cap, s->stamps_dev, count);
+  xs_status st = enqueue_batch_sorted(
+      s->reqs_dev, count, tiles, ps.precision, s->stamps_dev, E_all, m_all,
+      out_all, cap, [&] {
+        return lookup_batch_into(h, total, E_all, m_all, out_all, &ps,
+                                 ws + off_ws, lws, cap);
+      });
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(cap, &g);
+  if (st == XS_OK && ce != hipSuccess)
+    st = fail(XS_EHIP, "capturing the sorted batch failed: %s",
+              hipGetErrorString(ce));
+  if (st == XS_OK && s->sexec) {
+    hipGraphNode_t bad = nullptr;
+    hipGraphExecUpdateResult r = hipGraphExecUpdateSuccess;
+    if (hipGraphExecUpdate(s->sexec, g, &bad, &r) != hipSuccess ||
+        r != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(s->sexec);
+      s->sexec = nullptr;
+    }
+  }
+  if (st == XS_OK && !s->sexec) {
+    const hipError_t ie = hipGraphInstantiate(&s->sexec, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      s->sexec = nullptr;
+      st = fail(XS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+    }
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (st != XS_OK) return st;
+  XS_HIP(hipGraphLaunch(s->sexec, s->stream));
+  XS_HIP(hipEventRecord(s->done, s->stream));
+  return XS_OK;
+}
+
 }  // namespace
 }  // namespace xs
 
@@ -625,7 +720,11 @@ xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
   if (!s) return fail(XS_ENOMEM, "host allocation failed");
   s->tables = h;
   s->params = p;
-  s->user = (hipStream_t)stream;
+  if (params) {
+    s->user = *params;
+    s->has_user = true;
+  }
+  s->stream = (hipStream_t)stream;
   s->max_requests = max_requests;
   auto bail = [&](xs_status st) {
     stream_release(s);
@@ -645,6 +744,8 @@ xs_status xs_stream_create(xs_tables_t h, const xs_params* params,
       (st = hip(hipEventCreateWithFlags(&s->done, hipEventDisableTiming),
                 "hipEventCreate")) ||
       (st = hip(hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking),
+                "hipStreamCreateWithFlags")) ||
+      (st = hip(hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking),
                 "hipStreamCreateWithFlags")))
     return bail(st);
   int dev = 0, cus = 0, khz = 0;
@@ -737,6 +838,23 @@ xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
   XS_HIP(hipMemcpyAsync(s->reqs_dev, s->host, sizeof(ReqDev) * count,
                         hipMemcpyHostToDevice, s->upload));
   XS_HIP(hipStreamSynchronize(s->upload));
+
+  // Sorted mode when the parameters for this batch's size sort it (debug
+  // mode synchronises inside the lookup, which a capture cannot hold).
+  const int64_t total = begin;
+  if (total > 0 && total <= 0x7fffffffLL && !s->tables->d.dbg) {
+    xs_params ps;
+    if (xs_status st = xs_resolve_params(s->tables, total,
+                                         s->has_user ? &s->user : nullptr, &ps))
+      return st;
+    if (ps.sort != XS_SORT_NONE && total >= ps.sort_threshold) {
+      if (xs_status st = submit_sorted(s, count, tiles, total, ps)) return st;
+      s->last_sorted = true;
+      s->pending = count;
+      return XS_OK;
+    }
+  }
+  s->last_sorted = false;
   s->a_count = count;
   s->a_tiles = tiles;
   s->a_tag = tag;
@@ -744,8 +862,8 @@ xs_status xs_stream_submit(xs_stream_t s, const xs_request* reqs,
   const hipKernelNodeParams ip = init_params(s), rp = run_params(s);
   XS_HIP(hipGraphExecKernelNodeSetParams(s->exec, s->init_node, &ip));
   XS_HIP(hipGraphExecKernelNodeSetParams(s->exec, s->run_node, &rp));
-  XS_HIP(hipGraphLaunch(s->exec, s->user));
-  XS_HIP(hipEventRecord(s->done, s->user));
+  XS_HIP(hipGraphLaunch(s->exec, s->stream));
+  XS_HIP(hipEventRecord(s->done, s->stream));
   s->pending = count;
   return XS_OK;
 }

@@ -94,3 +94,72 @@ def test_stream_errors(env):
     st.close()
     with pytest.raises(xs.XsError):
         xs.xs_stream_create(env["h"], None, max_requests=0)
+
+
+def check_batch(env, reqs, spans, stats, makespan, prec):
+    ref = env["ref"] if prec == xs.XS_FP64 else env["ref32"]
+    assert len(stats) == len(spans)
+    for (E, m, out), (a, b), s in zip(reqs, spans, stats):
+        assert s["n"] == b - a
+        assert np.array_equal(out.cpu().numpy(), ref[a:b]), (a, b)
+        if b > a:
+            assert 0 <= s["start_us"] <= s["end_us"] <= makespan + 1e-6
+        else:
+            assert s["latency_us"] == 0
+
+
+@pytest.mark.parametrize("prec", [xs.XS_FP64, xs.XS_FP32])
+@pytest.mark.parametrize("grid", ["unionized", "hash", "nuclide"])
+def test_sorted_stream_matches_oracle(env, grid, prec):
+    """A stream whose parameters sort every batch runs the batch-sorted
+    pipeline captured into its graph: every request equals the oracle, every
+    request ends after the last one started (all are gathered, sorted and
+    looked up together), across replays of larger and smaller batches than
+    before (buffers grow, the graph is updated or rebuilt) with eager work in
+    between."""
+    say("sorted stream", grid, prec)
+    p = xs.make_params(prec, grid=grid, sort="band_material", sort_threshold=0)
+    st = xs.xs_stream_create(env["h"], p, max_requests=64)
+    rounds = [[1023, 4999, 30000], SIZES, SIZES[::-1][:5], SIZES]
+    for rnd, sizes in enumerate(rounds):
+        reqs, spans = batch(env, sizes, prec)
+        xs.xs_stream_submit(st, reqs)
+        stats, makespan = xs.xs_stream_wait(st)
+        check_batch(env, reqs, spans, stats, makespan, prec)
+        live = [s for s in stats if s["n"] > 0]
+        assert min(s["end_us"] for s in live) >= max(s["start_us"] for s in live)
+        eager = xs.xs_lookup_batch(env["h"], env["E"][:5000], env["m"][:5000],
+                                   params=xs.make_params(prec, grid=grid))
+        torch.cuda.synchronize()
+        ref = env["ref"] if prec == xs.XS_FP64 else env["ref32"]
+        assert np.array_equal(eager.cpu().numpy(), ref[:5000]), rnd
+    st.close()
+
+
+def test_stream_switches_between_modes(env):
+    """With a sort threshold of 50,000 lookups, batches below it run the
+    persistent kernel and batches above it the sorted pipeline, in any order
+    on one stream; with debug mode on every batch runs the persistent kernel
+    (the sorted pipeline's lookup cannot be captured while it synchronises).
+    Every request equals the oracle."""
+    say("stream modes")
+    prec = xs.XS_FP32
+    p = xs.make_params(prec, grid="unionized", sort="band_material",
+                       sort_threshold=50000, block_size=128)
+    st = xs.xs_stream_create(env["h"], p, max_requests=64)
+    small = [1, 63, 1023, 1025, 4999, 30000]          # 37,111 lookups
+    large = SIZES                                      # 101,135 lookups
+    for sizes in (small, large, small, large, large, small):
+        reqs, spans = batch(env, sizes, prec)
+        xs.xs_stream_submit(st, reqs)
+        stats, makespan = xs.xs_stream_wait(st)
+        check_batch(env, reqs, spans, stats, makespan, prec)
+    xs.xs_set_debug(env["h"], True)
+    try:
+        reqs, spans = batch(env, large, prec)
+        xs.xs_stream_submit(st, reqs)
+        stats, makespan = xs.xs_stream_wait(st)
+        check_batch(env, reqs, spans, stats, makespan, prec)
+    finally:
+        xs.xs_set_debug(env["h"], False)
+    st.close()
