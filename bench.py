@@ -141,11 +141,15 @@ def lookup_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_name(p) -> str:
+def kernel_name(p, pairs: bool = False) -> str:
     """The lookup kernel a resolved parameter set launches, as rocprofv3
-    names it (template arguments: grid, precision, LPT[, U or stage shape])."""
+    names it (template arguments: grid, precision, LPT[, U or stage shape];
+    for one wave per lookup: grid, precision and whether it reads the FP32
+    record pairs, which it does when the tables hold them)."""
     if getattr(p, "wave_per_lookup", 0) == 1:
-        return f"k_lookup_wave<{p.grid}, {p.precision}>"
+        use = bool(pairs and p.precision == 1 and p.grid != 1)
+        return (f"k_lookup_wave<{p.grid}, {p.precision}, "
+                f"{'true' if use else 'false'}>")
     if p.lds_stage:
         return (f"k_lookup_lds<{p.grid}, {p.precision}, {p.lookups_per_thread}, "
                 f"{p.lds_stage}>")
@@ -409,7 +413,8 @@ def sweep_in_flight(args, torch, synth, xs):
     tuned launch shape.  One JSON line per batch size."""
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
+             xs.XS_BUILD_UNION_BY_MATERIAL |
+             xs.XS_BUILD_FP32_PAIRS)
     extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
     h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
     ok = True
@@ -436,7 +441,8 @@ def request_stream(args, torch, synth, xs):
     oracle's FP32 form on 200,000 sampled lookups."""
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
+             xs.XS_BUILD_UNION_BY_MATERIAL |
+             xs.XS_BUILD_FP32_PAIRS)
     h = xs.xs_create_tables(t, flags, args.bins)
     line, ok = request_stream_line(
         args, torch, synth, xs, h, t, args.stream_requests,
@@ -597,7 +603,8 @@ def tuner_study(args, torch, synth, xs):
     n = args.study_n
     q = synth.config4_queries(5, n) if n <= 8_000_000 else synth.config2_queries(n)
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
+             xs.XS_BUILD_UNION_BY_MATERIAL |
+             xs.XS_BUILD_FP32_PAIRS)
     extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
     bins = [args.bins] + extra
     h = xs.xs_create_tables(t, flags, args.bins, extra_hash_bins=extra)
@@ -714,7 +721,8 @@ def energy_study(args, torch, synth, xs):
     q = synth.config2_queries(args.n)
     n = len(q)
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
+             xs.XS_BUILD_UNION_BY_MATERIAL |
+             xs.XS_BUILD_FP32_PAIRS)
     h = xs.xs_create_tables(t, flags, args.bins)
     E = torch.from_numpy(q.E).to("cuda:0")
     m = torch.from_numpy(q.mat).to("cuda:0")
@@ -778,7 +786,8 @@ def stream_study(args, torch, synth, xs):
     q = synth.config2_queries(args.n)
     n = len(q)
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
+             xs.XS_BUILD_UNION_BY_MATERIAL |
+             xs.XS_BUILD_FP32_PAIRS)
     h = xs.xs_create_tables(t, flags, args.bins)
     E = torch.from_numpy(q.E).to("cuda:0")
     m = torch.from_numpy(q.mat).to("cuda:0")
@@ -823,7 +832,8 @@ def event_study(args, torch, synth, xs):
     method.  Histories/s is the paper's figure of merit (particles/s)."""
     t = synth.config2_tables()
     flags = (xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_UNIONIZED |
-             xs.XS_BUILD_UNION_BY_MATERIAL)
+             xs.XS_BUILD_UNION_BY_MATERIAL |
+             xs.XS_BUILD_FP32_PAIRS)
     h = xs.xs_create_tables(t, flags, args.bins)
     H = args.event_histories
     rows = []
@@ -981,7 +991,7 @@ def main(argv=None):
     t = synth.config2_tables()
     q = synth.config2_queries(args.n)
     nbar = synth.mean_nuclides(t, q)
-    flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH
+    flags = xs.XS_BUILD_FP32 | xs.XS_BUILD_HASH | xs.XS_BUILD_FP32_PAIRS
     if not args.no_union:
         flags |= xs.XS_BUILD_UNIONIZED | xs.XS_BUILD_UNION_BY_MATERIAL
     extra = [b for b in EXTRA_HASH_BINS if b != args.bins]
@@ -1010,7 +1020,8 @@ def main(argv=None):
         fn, out = runner(params)
         sec = time_steps(fn, args.steps, args.warmup)
         kt = kernel_time(xs, h, fn, max(args.steps, 3))
-        kname = kernel_name(params)
+        kname = kernel_name(params, pairs=bool(
+            xs.xs_table_info(h)["build_flags"] & xs.XS_BUILD_FP32_PAIRS))
         traffic = measured_traffic(kname, params.block_size, n)
         rl = roofline(n, nbar, params.precision, kt["ms_lookup"], traffic)
         rl["kernel"] = kname

@@ -94,6 +94,14 @@ typedef int32_t xs_status;
  * then reads L_m contiguous indices instead of a K-wide row; memory is
  * U * sum(L_m) * 4 bytes instead of U * K * 4. */
 #define XS_BUILD_UNION_BY_MATERIAL 8u
+/* With XS_BUILD_FP32: also store each grid interval's two FP32 records side
+ * by side in a 64-byte aligned block (64 more bytes per grid point).  A
+ * lookup that reads its bracket of each nuclide from global memory (the
+ * one-wave-per-lookup kernel, union or bisection grid) then touches one
+ * aligned 64-byte block per nuclide instead of two neighbouring 32-byte
+ * records, which cross a 128-byte line for one interval in four.  Results
+ * are unchanged. */
+#define XS_BUILD_FP32_PAIRS 16u
 
 typedef struct xs_tables_s* xs_tables_t;
 
@@ -201,7 +209,7 @@ typedef struct {
                                 counts: the key of tuned-parameter caches */
   size_t bytes_grid;         /* search grid (FP64 energies) */
   size_t bytes_fp64;         /* FP64 interpolation records */
-  size_t bytes_fp32;         /* FP32 interpolation records */
+  size_t bytes_fp32;         /* FP32 interpolation records (and pairs) */
   size_t bytes_materials;    /* material lists */
   size_t bytes_hash;         /* hash-bin index table */
   size_t bytes_union;        /* union grid + its index table */

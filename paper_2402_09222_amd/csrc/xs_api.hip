@@ -160,11 +160,13 @@ xs_status validate_desc(const xs_table_desc* d) {
   if (!d->mat_offsets || !d->mat_nuclides || !d->mat_density)
     return fail(XS_EINVAL, "material arrays must not be NULL");
   if (d->build_flags & ~(XS_BUILD_FP32 | XS_BUILD_HASH | XS_BUILD_UNIONIZED |
-                         XS_BUILD_UNION_BY_MATERIAL))
+                         XS_BUILD_UNION_BY_MATERIAL | XS_BUILD_FP32_PAIRS))
     return fail(XS_EINVAL, "unknown build flag bits 0x%x", d->build_flags);
   if ((d->build_flags & XS_BUILD_UNION_BY_MATERIAL) &&
       !(d->build_flags & XS_BUILD_UNIONIZED))
     return fail(XS_EINVAL, "XS_BUILD_UNION_BY_MATERIAL needs XS_BUILD_UNIONIZED");
+  if ((d->build_flags & XS_BUILD_FP32_PAIRS) && !(d->build_flags & XS_BUILD_FP32))
+    return fail(XS_EINVAL, "XS_BUILD_FP32_PAIRS needs XS_BUILD_FP32");
   if ((d->build_flags & XS_BUILD_HASH) &&
       (d->n_hash_bins < 1 || d->n_hash_bins > 100000))
     return fail(XS_EINVAL, "n_hash_bins must be in [1, 100000]");
@@ -700,6 +702,22 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
     if ((st = upload(h, rec32.data(), rec32.size(), &r32, s))) return cleanup(st);
     d.rec32 = r32;
   }
+  // kept until the function returns, like the other host arrays whose
+  // copies are in flight
+  std::vector<Rec32> pairs;
+  size_t pair_bytes = 0;
+  if (!rec32.empty() && (desc->build_flags & XS_BUILD_FP32_PAIRS)) {
+    pairs.resize(2 * (size_t)P);
+    for (int k = 0; k < K; ++k)
+      for (int64_t p = goff[k]; p < goff[k + 1]; ++p) {
+        pairs[2 * p] = rec32[p];
+        pairs[2 * p + 1] = rec32[p + 1 < goff[k + 1] ? p + 1 : p];
+      }
+    Rec32* pr;
+    if ((st = upload(h, pairs.data(), pairs.size(), &pr, s))) return cleanup(st);
+    d.pair32 = pr;
+    pair_bytes = pairs.size() * sizeof(Rec32);
+  }
 
   xs_table_info_t& info = h->info;
   info.n_nuclides = K;
@@ -711,7 +729,7 @@ xs_status xs_create_tables(const xs_table_desc* desc, void* stream,
   info.e_max = e_max;
   info.bytes_grid = (size_t)P * 8;
   info.bytes_fp64 = (size_t)P * sizeof(Rec64);
-  info.bytes_fp32 = rec32.size() * sizeof(Rec32);
+  info.bytes_fp32 = rec32.size() * sizeof(Rec32) + pair_bytes;
   info.bytes_materials = (size_t)(M + 1) * 4 + (size_t)L * (sizeof(MatRec) + 8);
 
   if (desc->build_flags & XS_BUILD_HASH) {

@@ -49,6 +49,9 @@ struct DevTables {
   const double* E;           // [P] search grid
   const Rec64* rec64;        // [P]
   const Rec32* rec32;        // [P] (null unless built)
+  // [2P]: pair32[2p], pair32[2p + 1] = records p and p + 1 of a nuclide
+  // (the last point of a nuclide repeats itself); null unless built
+  const Rec32* pair32;
   const int32_t* moff;       // [M+1]
   const MatRec* mrec;        // [sum L]
   const double* rho64;       // [sum L]

@@ -990,9 +990,14 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
 
 constexpr int kWaveBlock = 256;  // largest block: four waves
 
-template <int GRID, int PREC>
+// PAIRS (FP32, union or bisection grid, XS_BUILD_FP32_PAIRS built): a
+// bracket's two records come from one aligned 64-byte block of the pair
+// table instead of two neighbouring records (same values, same results).
+template <int GRID, int PREC, bool PAIRS>
 __global__ __launch_bounds__(kWaveBlock) void k_lookup_wave(const DevTables t,
                                                             const LookupArgs a) {
+  static_assert(!PAIRS || (PREC == XS_FP32 && GRID != XS_GRID_HASH),
+                "pairs serve FP32 brackets found exactly");
   using R = typename RecOf<PREC>::T;
   using T = typename Acc<PREC>::Term;
   __shared__ T terms[kWaveBlock / 64][64][XS_CHANNELS];
@@ -1026,10 +1031,16 @@ __global__ __launch_bounds__(kWaveBlock) void k_lookup_wave(const DevTables t,
     if (j < j1) {
       const MatRec r = t.mrec[j];
       const int cand = loc.start(t, r, j, e);
-      Window<GRID, PREC> win;
-      win.load(t, r, cand);
       R lo, hi;
-      win.finish(t, r, loc, cand, e, lo, hi);
+      if constexpr (PAIRS) {
+        const R* pp = t.pair32 + 2 * ((int64_t)r.base + cand);
+        lo = pp[0];
+        hi = pp[1];
+      } else {
+        Window<GRID, PREC> win;
+        win.load(t, r, cand);
+        win.finish(t, r, loc, cand, e, lo, hi);
+      }
       T tm[XS_CHANNELS];
       Acc<PREC>::terms(lo, hi, e, Acc<PREC>::rho(t, r, j), tm);
 #pragma unroll
@@ -1095,12 +1106,20 @@ hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
     const int64_t nb = (a.n + per_block - 1) / per_block;
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
-    if (p.precision == XS_FP64)
-      hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP64>), dim3((unsigned)nb),
-                         dim3(p.block_size), 0, s, t, a);
-    else
-      hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP32>), dim3((unsigned)nb),
-                         dim3(p.block_size), 0, s, t, a);
+    if (p.precision == XS_FP64) {
+      hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP64, false>),
+                         dim3((unsigned)nb), dim3(p.block_size), 0, s, t, a);
+    } else if constexpr (GRID != XS_GRID_HASH) {
+      if (t.pair32)
+        hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP32, true>),
+                           dim3((unsigned)nb), dim3(p.block_size), 0, s, t, a);
+      else
+        hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP32, false>),
+                           dim3((unsigned)nb), dim3(p.block_size), 0, s, t, a);
+    } else {
+      hipLaunchKernelGGL((k_lookup_wave<GRID, XS_FP32, false>),
+                         dim3((unsigned)nb), dim3(p.block_size), 0, s, t, a);
+    }
     return hipGetLastError();
   }
   if (p.lds_stage) {

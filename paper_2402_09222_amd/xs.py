@@ -26,6 +26,7 @@ XS_SORT_BAND_MATERIAL = 4
 XS_QUEUE_COMPACT, XS_QUEUE_PREDICATED = 0, 1
 XS_BUILD_FP32, XS_BUILD_HASH, XS_BUILD_UNIONIZED = 1, 2, 4
 XS_BUILD_UNION_BY_MATERIAL = 8
+XS_BUILD_FP32_PAIRS = 16
 XS_MAX_HASH_GRIDS = 8
 XS_NOALLOC_SCRATCH_BYTES = 128 << 20
 XS_NOALLOC_MAX_SORTED = 8259456

@@ -143,7 +143,11 @@ def test_create_rejects_structure(lib):
     assert _create_status(t, n_channels=4)[0] == xs.XS_ETABLE
     assert _create_status(t, n_nuclides=0)[0] == xs.XS_ETABLE
     assert _create_status(t, n_materials=0)[0] == xs.XS_ETABLE
-    assert _create_status(t, flags=16)[0] == xs.XS_EINVAL
+    assert _create_status(t, flags=32)[0] == xs.XS_EINVAL
+    # FP32 record pairs need the FP32 records
+    assert _create_status(t, flags=xs.XS_BUILD_FP32_PAIRS)[0] == xs.XS_EINVAL
+    assert _create_status(t, flags=xs.XS_BUILD_FP32_PAIRS |
+                          xs.XS_BUILD_HASH, bins=4)[0] == xs.XS_EINVAL
     assert _create_status(t, flags=xs.XS_BUILD_UNION_BY_MATERIAL)[0] == xs.XS_EINVAL
     assert _create_status(t, flags=xs.XS_BUILD_HASH, bins=0)[0] == xs.XS_EINVAL
     assert _create_status(t, flags=xs.XS_BUILD_HASH, bins=100001)[0] == xs.XS_EINVAL

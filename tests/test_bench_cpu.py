@@ -82,5 +82,10 @@ def test_kernel_names_and_traffic_keys():
     assert bench.kernel_name(p) == "k_lookup<0, 0, 1, 2>"
     p = xs.make_params(xs.XS_FP32, grid=1, lookups_per_thread=1, unroll=1,
                        lds_stage=0, wave_per_lookup=1)
-    assert bench.kernel_name(p) == "k_lookup_wave<1, 1>"
+    assert bench.kernel_name(p) == "k_lookup_wave<1, 1, false>"
+    assert bench.kernel_name(p, pairs=True) == "k_lookup_wave<1, 1, false>"
+    p.grid = 2
+    assert bench.kernel_name(p, pairs=True) == "k_lookup_wave<2, 1, true>"
+    p.precision = 0
+    assert bench.kernel_name(p, pairs=True) == "k_lookup_wave<2, 0, false>"
     assert bench.measured_traffic("no such kernel", 128, 10) is None

@@ -513,6 +513,35 @@ def test_worked_examples_exact(golden):
         h.close()
 
 
+@pytest.mark.parametrize("grid", ["unionized", "nuclide", "hash"])
+def test_wave_kernel_reads_record_pairs(cfg1, grid):
+    """With XS_BUILD_FP32_PAIRS the one-wave-per-lookup kernel of the FP32
+    form reads each bracket as one aligned 64-byte pair (union and bisection
+    grids; the hash grid keeps its three-record window): same bits as the
+    oracle's FP32 form and as the kernel on a handle without pairs, sorted
+    and unsorted; the pairs add 64 bytes per grid point."""
+    say("pairs", grid)
+    t = cfg1["t"]
+    h = xs.xs_create_tables(t, ALL_FLAGS | xs.XS_BUILD_FP32_PAIRS, 4000)
+    try:
+        info, base = xs.xs_table_info(h), xs.xs_table_info(cfg1["h"])
+        assert info["bytes_fp32"] == base["bytes_fp32"] + 64 * info["n_points"]
+        for sort in ("none", "energy"):
+            p = xs.make_params(xs.XS_FP32, grid=grid, sort=sort,
+                               sort_threshold=0, block_size=256,
+                               lookups_per_thread=1, unroll=1, lds_stage=0,
+                               wave_per_lookup=1)
+            out = xs.xs_lookup_batch(h, cfg1["E"], cfg1["m"], params=p)
+            plain = xs.xs_lookup_batch(cfg1["h"], cfg1["E"], cfg1["m"],
+                                       params=p)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            assert np.array_equal(got, cfg1["ref32"]), sort
+            assert np.array_equal(got, plain.cpu().numpy()), sort
+    finally:
+        h.close()
+
+
 def test_wave_union_search_dense_and_sparse_bins():
     """The wave kernel's union search reads one logarithmic bin's points at
     once; a bin holding 64 points or more, and energies that the rounding of
