@@ -10,7 +10,11 @@ Two forms are timed for the headline: the plain FP64 lookup (per-nuclide
 bisection, no sort, 256-lane blocks, one lookup per lane) and the FP32 form
 with parameters chosen by the library's tuner; `value` is the latter.  The
 FP64 form tuned the same way is timed beside them (`tuned_fp64`), so the
-FP32 form's gain over plain FP64 splits into method and precision.  The JSON line carries
+FP32 form's gain over plain FP64 splits into method and precision.  Each
+step is one batch sorted and looked up, start to end, on one stream; the
+same steps alternating over two streams (one step's sort overlapping the
+previous step's lookup, as a serving loop would run them) are timed beside
+it (`tuned_fp32.two_streams`, outside `value`).  The JSON line carries
 the dominant kernel's roofline (algorithmic flops or bytes per launch /
 average kernel time from HIP events on the launch stream, against the
 vendor peaks, with the issue ceiling and the demand and measured HBM
@@ -1015,6 +1019,29 @@ def main(argv=None):
             xs.xs_lookup_batch(h, E, m, out=out, params=params, workspace=ws)
         return fn, out
 
+    def two_streams(params, serial_out):
+        """The same steps issued alternately on two streams, each with its
+        own workspace and output (a serving loop's double buffering): one
+        step's sort overlaps the previous step's lookup.  Outside `value`;
+        both outputs must equal the serial step's."""
+        sts = [torch.cuda.Stream(), torch.cuda.Stream()]
+        nb = xs.xs_workspace_size(h, n, params)
+        wss = [xs._workspace(nb, E.device) for _ in sts]
+        outs = [torch.empty((n, 5), device="cuda:0", dtype=torch.float32)
+                for _ in sts]
+        k = [0]
+
+        def fn():
+            j = k[0] % 2
+            k[0] += 1
+            xs.xs_lookup_batch(h, E, m, out=outs[j], params=params,
+                               workspace=wss[j], stream=sts[j])
+        torch.cuda.synchronize()
+        sec = time_steps(fn, args.steps, args.warmup)
+        same = all(np.array_equal(o.cpu().numpy(), serial_out) for o in outs)
+        return {"value": n / sec, "ms_per_step": sec * 1e3, "streams": 2,
+                "equal_to_serial_steps": bool(same)}
+
     def measure(params):
         params = xs.xs_resolve_params(h, n, params)
         fn, out = runner(params)
@@ -1070,6 +1097,11 @@ def main(argv=None):
         tuned["tuner"] = tune_report
         log(f"FP32 tuned: {tuned['value']:.4g} lookups/s, "
             f"{tuned['ms_per_step']:.3f} ms/step")
+        if args.only is None:
+            tuned["two_streams"] = two_streams(
+                xs.xs_resolve_params(h, n, p32), out_tuned)
+            log(f"FP32 tuned, steps alternating over two streams: "
+                f"{tuned['two_streams']['value']:.4g} lookups/s")
 
     # The FP64 form tuned the same way: what the sort, the union index and
     # LDS staging give without the narrower data, so the FP32 form's gain
@@ -1180,6 +1212,10 @@ def main(argv=None):
         return 1
     if not extras_ok:
         log("PARITY FAILURE in the extras (in-flight sweep or request stream)")
+        return 1
+    if tuned and "two_streams" in tuned and \
+            not tuned["two_streams"]["equal_to_serial_steps"]:
+        log("PARITY FAILURE: two-stream steps differ from the serial steps")
         return 1
     return 0
 
