@@ -7,9 +7,10 @@
 // a lookup's value.  Here the key is a 32-bit word: an optional inactive
 // flag, the material, and the top bits of the energy's IEEE pattern above
 // the table's lowest energy (monotone in E for positive doubles).  Each
-// 8-bit digit pass is reduce-then-scan: per-tile digit histograms, a scan to
-// global offsets, then a scatter whose ranks inside a 64-lane wave come from
-// per-wave LDS counters.
+// 8-bit digit pass is reduce-then-scan: per-tile digit histograms, a scan
+// of each digit's counts over the tiles, then a scatter that adds the
+// digits' starts and whose ranks inside a 64-lane wave come from per-wave
+// LDS counters.
 #include "xs_internal.h"
 
 namespace xs {
@@ -83,7 +84,9 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x,
   return incl + off;
 }
 
-// Per-tile digit histogram, digit-major: hist[d * nT + tile].
+// Per-tile digit histogram, digit-major: hist[d * nT + tile].  A block's
+// keys are all read before any is counted, so its loads are in flight
+// together.
 template <bool FROM_INPUT>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
     SortSrc src, const uint32_t* __restrict__ keys_in, int shift,
@@ -91,41 +94,32 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
   __shared__ uint32_t h[kRadixBins];
   const int tid = threadIdx.x;
   h[tid] = 0;
-  __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+  uint32_t key[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = base + r * kSortThreads + tid;
-    if (i < src.n) {
-      const uint32_t key = FROM_INPUT ? src_key(src, i) : keys_in[i];
-      atomicAdd(&h[(key >> shift) & (kRadixBins - 1)], 1u);
-    }
+    key[r] = i < src.n ? (FROM_INPUT ? src_key(src, i) : keys_in[i]) : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + r * kSortThreads + tid;
+    if (i < src.n) atomicAdd(&h[(key[r] >> shift) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
   hist[(int64_t)tid * nT + blockIdx.x] = h[tid];
 }
 
-// totals[d] = sum of row d.
-__global__ __launch_bounds__(256) void k_digit_totals(
-    const uint32_t* __restrict__ hist, int32_t nT, uint32_t* __restrict__ totals) {
-  const uint32_t* row = hist + (int64_t)blockIdx.x * nT;
-  uint32_t s = 0;
-  for (int i = threadIdx.x; i < nT; i += 256) s += row[i];
-  uint32_t tot;
-  block_incl_scan<256>(s, &tot);
-  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
-}
-
-// Row d becomes its exclusive scan plus the count of all smaller digits:
-// hist[d * nT + tile] = first output position of digit d from that tile.
+// Row d becomes its exclusive scan over the tiles (the position of the
+// tile's first key of digit d among the digit's keys); totals[d] gets the
+// row's sum.  The digits' starts (the exclusive scan of totals) are added
+// by the scatter.
 __global__ __launch_bounds__(256) void k_row_scan(
-    uint32_t* __restrict__ hist, int32_t nT, const uint32_t* __restrict__ totals) {
+    uint32_t* __restrict__ hist, int32_t nT, uint32_t* __restrict__ totals) {
   const int d = blockIdx.x;
-  uint32_t base;
-  block_incl_scan<256>(threadIdx.x < (unsigned)d ? totals[threadIdx.x] : 0u,
-                       &base);
   uint32_t* row = hist + (int64_t)d * nT;
-  uint32_t carry = base;
+  uint32_t carry = 0;
   for (int c0 = 0; c0 < nT; c0 += 256) {
     const int i = c0 + threadIdx.x;
     const uint32_t x = i < nT ? row[i] : 0u;
@@ -134,6 +128,7 @@ __global__ __launch_bounds__(256) void k_row_scan(
     if (i < nT) row[i] = carry + incl - x;
     carry += tot;
   }
+  if (threadIdx.x == 0) totals[d] = carry;
 }
 
 // Stable scatter of one digit pass.  Wave w of the block owns the tile's
@@ -152,8 +147,9 @@ template <bool FROM_INPUT, bool WRITE_KEYS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     SortSrc src, const uint32_t* __restrict__ keys_in,
     const uint32_t* __restrict__ vals_in, int shift,
-    const uint32_t* __restrict__ offs, int32_t nT,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t* __restrict__ offs, const uint32_t* __restrict__ totals,
+    int32_t nT, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
   constexpr int kWaves = kSortThreads / 64;
   constexpr int kPerWave = kSortTile / kWaves;
   static_assert(kSortThreads == kRadixBins, "one thread per digit");
@@ -207,7 +203,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       wcnt[ww][tid] = s;
       s += c[ww];
     }
-    gdelta[tid] = (int32_t)(tile_off - start);
+    // the digit's first output position: the keys of all smaller digits
+    const uint32_t td = totals[tid];
+    const uint32_t dstart = block_incl_scan<kSortThreads>(td, &all) - td;
+    gdelta[tid] = (int32_t)((int64_t)dstart + tile_off - start);
   }
   __syncthreads();
 #pragma unroll
@@ -337,26 +336,24 @@ hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
     else
       hipLaunchKernelGGL((k_radix_hist<false>), dim3(nT), dim3(kSortThreads), 0,
                          s, src, bufk[cur], shift, hist, nT);
-    hipLaunchKernelGGL(k_digit_totals, dim3(kRadixBins), dim3(256), 0, s, hist,
-                       nT, totals);
     hipLaunchKernelGGL(k_row_scan, dim3(kRadixBins), dim3(256), 0, s, hist, nT,
                        totals);
     if (first && last)
       hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(nT),
                          dim3(kSortThreads), 0, s, src, nullptr, nullptr, shift,
-                         hist, nT, bufk[dst], bufv[dst]);
+                         hist, totals, nT, bufk[dst], bufv[dst]);
     else if (first)
       hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3(nT),
                          dim3(kSortThreads), 0, s, src, nullptr, nullptr, shift,
-                         hist, nT, bufk[dst], bufv[dst]);
+                         hist, totals, nT, bufk[dst], bufv[dst]);
     else if (last)
       hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(nT),
                          dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
-                         shift, hist, nT, bufk[dst], bufv[dst]);
+                         shift, hist, totals, nT, bufk[dst], bufv[dst]);
     else
       hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(nT),
                          dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
-                         shift, hist, nT, bufk[dst], bufv[dst]);
+                         shift, hist, totals, nT, bufk[dst], bufv[dst]);
     cur = dst;
   }
   *perm_out = (const int32_t*)bufv[cur];
