@@ -208,6 +208,40 @@ def test_edge_queries(cfg1):
     assert np.all(np.isnan(ref[-6:]))
 
 
+@pytest.mark.parametrize("shape", [dict(lookups_per_thread=1, block_size=128,
+                                         lds_stage=1),
+                                    dict(lookups_per_thread=2, block_size=64,
+                                         lds_stage=3)])
+@pytest.mark.parametrize("invalid", [0.0, 0.05])
+def test_staged_blocks_of_several_materials(cfg1, shape, invalid):
+    """Sorted, LDS-staged batches: a block that straddles two groups of the
+    sort key (or holds invalid queries) stages the material most of its
+    lookups share and walks the others per lane; with 5 % invalid queries
+    spread over the batch most blocks are of that kind.  Every valid query
+    matches the oracle, every invalid one is NaN, in both precisions and
+    every grid."""
+    say("mixed blocks", shape, invalid)
+    t, q = cfg1["t"], cfg1["q"]
+    E = q.E.copy()
+    m = q.mat.copy()
+    bad = np.zeros(len(E), bool)
+    if invalid:
+        pick = synth.Stream(41, 2).uniform(len(E)) < invalid
+        bad = pick
+        E[pick & (np.arange(len(E)) % 2 == 0)] = -1.0
+        m[pick & (np.arange(len(E)) % 2 == 1)] = t.n_materials
+    ref = oracle.lookup(t, E, m)
+    ref32 = oracle.lookup_f32(t, E, m)
+    Ed, md = dev(E, torch.float64), dev(m, torch.int32)
+    for grid in ("unionized", "nuclide", "hash"):
+        for sort in ("band_material", "material_energy"):
+            for prec, want in ((xs.XS_FP64, ref), (xs.XS_FP32, ref32)):
+                out = run(cfg1["h"], Ed, md, precision=prec, grid=grid,
+                          sort=sort, sort_threshold=0, unroll=1, **shape)
+                np.testing.assert_array_equal(out, want)
+    assert np.isnan(ref[bad]).all() and not np.isnan(ref[~bad]).any()
+
+
 def test_empty_and_tiny(cfg1):
     h = cfg1["h"]
     E = cfg1["E"][:0]
