@@ -215,11 +215,10 @@ def test_edge_queries(cfg1):
 @pytest.mark.parametrize("invalid", [0.0, 0.05])
 def test_staged_blocks_of_several_materials(cfg1, shape, invalid):
     """Sorted, LDS-staged batches: a block that straddles two groups of the
-    sort key (or holds invalid queries) stages the material most of its
-    lookups share and walks the others per lane; with 5 % invalid queries
-    spread over the batch most blocks are of that kind.  Every valid query
-    matches the oracle, every invalid one is NaN, in both precisions and
-    every grid."""
+    sort key (or holds invalid queries) takes the per-lane walk instead of
+    the staged one; with 5 % invalid queries spread over the batch most
+    blocks are of that kind.  Every valid query matches the oracle, every
+    invalid one is NaN, in both precisions and every grid."""
     say("mixed blocks", shape, invalid)
     t, q = cfg1["t"], cfg1["q"]
     E = q.E.copy()
