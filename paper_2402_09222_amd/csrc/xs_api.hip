@@ -522,7 +522,28 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
 
   LookupArgs a{n, E, mat, nullptr, nullptr, masked ? active : nullptr, out};
   if (do_sort) {
-    XS_HIP(launch_sort(key, n, E, mat, masked ? active : nullptr, ws, &a.perm, s));
+    // The LDS-staged kernel over a key with the material in it gets block
+    // ranges cut at every group of the key (bits above the energy rest), so
+    // no block holds two materials; when the key has few enough groups
+    // (at most one per four blocks) and the batch is not tiny.  Only for
+    // the narrow-window stage shapes (1, 2; dense batches): with the wide
+    // windows of shape 3 the per-lane walk of the few straddling blocks
+    // costs less than finding the groups (measured from 5e5 to 2e6).
+    const int rest = key.e_bits - key.band_bits;
+    const int group_bits = key.total_bits - rest;
+    const int64_t per_block = (int64_t)p.block_size * p.lookups_per_thread;
+    const int64_t nb = (n + per_block - 1) / per_block;
+    const bool cut = p.lds_stage > 0 && p.lds_stage <= 2 && key.mat_bits > 0 &&
+                     p.sort != XS_SORT_ENERGY && n >= 4096 &&
+                     group_bits < 31 &&
+                     ((int64_t)1 << group_bits) <= std::max<int64_t>(1, nb / 4);
+    const uint32_t* keys = nullptr;
+    uint32_t* spare = nullptr;
+    XS_HIP(launch_sort(key, n, E, mat, masked ? active : nullptr, ws, &a.perm,
+                       cut ? &keys : nullptr, &spare, s));
+    if (cut)
+      XS_HIP(launch_block_ranges(keys, n, rest, (int64_t)1 << group_bits,
+                                 per_block, spare, &a, s));
   } else if (compact) {
     XS_HIP(launch_compact(n, active, ws, &a.perm, &a.count_dev, s));
     a.active = nullptr;

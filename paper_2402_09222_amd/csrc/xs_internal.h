@@ -222,6 +222,13 @@ struct LookupArgs {
   const int64_t* count_dev;
   const uint8_t* active;   // null = all active
   void* out;
+  // LDS-staged kernel over a sorted queue: block v covers the queue
+  // positions [blocks[2v], blocks[2v + 1]), each range inside one group of
+  // the sort key, for v < *n_blocks (launched as max_blocks blocks); null:
+  // block v covers the next block_size * lookups-per-lane positions
+  const int32_t* blocks = nullptr;
+  const int32_t* n_blocks = nullptr;
+  int64_t max_blocks = 0;
 };
 hipError_t launch_lookup_nuclide(const DevTables& t, const xs_params& p,
                                  const LookupArgs& a, hipStream_t s);
@@ -244,10 +251,22 @@ hipError_t launch_indices_union(const DevTables& t, int64_t n, const double* E,
 size_t sort_workspace_bytes(int64_t n, int total_bits);
 size_t compact_workspace_bytes(int64_t n);
 // Sorts lookups by `key`; on return *perm_out points into ws at the
-// permutation (sorted position -> input index).
+// permutation (sorted position -> input index).  With keys_out, the sorted
+// keys are written too (*keys_out), and *spare points at n words of ws the
+// sort no longer needs.
 hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
                        const int32_t* mat, const uint8_t* active, void* ws,
-                       const int32_t** perm_out, hipStream_t s);
+                       const int32_t** perm_out, const uint32_t** keys_out,
+                       uint32_t** spare, hipStream_t s);
+// Block ranges of the LDS-staged kernel over sorted keys: the queue is cut
+// at every change of key >> gshift (groups of one material) and each group
+// into pieces of per_block positions.  groups = the number of possible
+// values of key >> gshift; the ranges, their count and the starts use
+// 8 * (2 * groups + 2 + n / per_block) + 256 bytes of `spare`.  Sets
+// a->blocks, a->n_blocks and a->max_blocks (an upper bound of the count).
+hipError_t launch_block_ranges(const uint32_t* keys, int64_t n, int gshift,
+                               int64_t groups, int64_t per_block, void* spare,
+                               LookupArgs* a, hipStream_t s);
 // Stable compaction of active slots: perm (in ws) lists them in input
 // order, *count_out (device) their number.
 hipError_t launch_compact(int64_t n, const uint8_t* active, void* ws,

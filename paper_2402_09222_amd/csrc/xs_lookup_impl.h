@@ -18,6 +18,8 @@
 // scalar loads.
 #pragma once
 
+#include <type_traits>
+
 #include "xs_internal.h"
 
 namespace xs {
@@ -765,6 +767,12 @@ template <int PREC, int SHAPE>
 constexpr int lds_window() {
   return (PREC == XS_FP64 ? 3 : 4) * (256 / lds_group<SHAPE>()) / 4;
 }
+//
+// Over a sorted queue cut at every group of the sort key (a.blocks), a
+// block's range holds one material, and the lanes past the range's end (the
+// group's last, partial piece) idle through the staged walk.  A block with
+// lookups of several materials (an uncut queue straddling two groups), or
+// whose first lookup is invalid, takes the per-lane walk.
 template <int GRID, int PREC, int LPT, int SHAPE>
 __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
                                                            const LookupArgs a) {
@@ -780,18 +788,25 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
   __shared__ double s_red[2][16];
   const int tid = threadIdx.x;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t n = a.count_dev ? *a.count_dev : a.n;
-  const int64_t first = blk * (int64_t)blockDim.x * LPT + tid;
+  int64_t first, end;  // this block's queue positions: first .. end - 1
+  if (a.blocks) {
+    if (blk >= *a.n_blocks) return;  // the whole block leaves
+    first = a.blocks[2 * blk];
+    end = a.blocks[2 * blk + 1];
+  } else {
+    first = blk * (int64_t)blockDim.x * LPT;
+    end = a.count_dev ? *a.count_dev : a.n;
+  }
 
-  // Lane tid takes queue positions first, first + blockDim, ... (coalesced).
+  // Lane tid takes queue positions first + tid, + blockDim, ... (coalesced).
   bool act[LPT];
   int64_t o[LPT];
   double e[LPT];
   int m[LPT];
 #pragma unroll
   for (int l = 0; l < LPT; ++l) {
-    const int64_t q = first + (int64_t)l * blockDim.x;
-    act[l] = q < n;
+    const int64_t q = first + tid + (int64_t)l * blockDim.x;
+    act[l] = q < end;
     o[l] = 0;
     e[l] = 1.0;
     m[l] = -1;
@@ -809,12 +824,17 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
       }
     }
   }
+  // One material: every active lane's is the first lane's (lanes past the
+  // range's end and invalid queries do not count).
   if (tid == 0) s_mat = act[0] ? m[0] : -1;
   __syncthreads();
   const int mb = s_mat;
-  bool mine = mb >= 0;
+  bool mine = mb >= 0, full = true;
 #pragma unroll
-  for (int l = 0; l < LPT; ++l) mine = mine && act[l] && m[l] == mb;
+  for (int l = 0; l < LPT; ++l) {
+    mine = mine && (!act[l] || m[l] == mb);
+    full = full && act[l];
+  }
   const bool uniform = __syncthreads_and(mine);
 
   if (!uniform) {
@@ -831,13 +851,31 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
     }
     return;
   }
+  const bool whole = __syncthreads_and(full);
 
-  // Block energy range (all lookups of the block are active here).
-  double lo_e = e[0], hi_e = e[0];
+  // The staged walk; with idle lanes (masked), they compute nothing they
+  // keep and stay out of the block's energy range.
+  auto staged = [&](auto masked) {
+  constexpr bool kMasked = decltype(masked)::value;
+  // Block energy range (over the active lookups).
+  double lo_e, hi_e;
+  if constexpr (kMasked) {
+    lo_e = __builtin_inf();
+    hi_e = -__builtin_inf();
 #pragma unroll
-  for (int l = 1; l < LPT; ++l) {
-    lo_e = fmin(lo_e, e[l]);
-    hi_e = fmax(hi_e, e[l]);
+    for (int l = 0; l < LPT; ++l)
+      if (act[l]) {
+        lo_e = fmin(lo_e, e[l]);
+        hi_e = fmax(hi_e, e[l]);
+      }
+  } else {
+    lo_e = e[0];
+    hi_e = e[0];
+#pragma unroll
+    for (int l = 1; l < LPT; ++l) {
+      lo_e = fmin(lo_e, e[l]);
+      hi_e = fmax(hi_e, e[l]);
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -973,7 +1011,13 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
     __syncthreads();  // the stage and window tables are rewritten next group
   }
 #pragma unroll
-  for (int l = 0; l < LPT; ++l) acc[l].store(a.out, o[l]);
+  for (int l = 0; l < LPT; ++l)
+    if (!kMasked || act[l]) acc[l].store(a.out, o[l]);
+  };
+  if (whole)
+    staged(std::false_type{});
+  else
+    staged(std::true_type{});
 }
 
 // ---- one wave per lookup ------------------------------------------------------------
@@ -1129,7 +1173,8 @@ hipError_t launch_grid_method(const DevTables& t, const xs_params& p,
       return hipErrorInvalidValue;
     if (p.lds_stage < 1 || p.lds_stage > 3) return hipErrorInvalidValue;
     const int64_t per_block = (int64_t)p.block_size * lpt;
-    const int64_t nb = (a.n + per_block - 1) / per_block;
+    const int64_t nb =
+        a.blocks ? a.max_blocks : (a.n + per_block - 1) / per_block;
     if (nb == 0) return hipSuccess;
     if (nb > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 grid((unsigned)nb), block((unsigned)p.block_size);

@@ -293,9 +293,108 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_scatter(
   }
 }
 
+// ---- block ranges over a sorted queue -------------------------------------
+//
+// The LDS-staged lookup shares one material's windows across a block, so a
+// block that straddles two groups of the sort key (two materials) falls
+// back to the per-lane walk.  Cutting the queue at every group and each
+// group into block-sized pieces removes such blocks; a group's last piece
+// is partly idle instead.
+
+// starts[g] = the number of keys with key >> gshift < g, for g in
+// [0, groups]: one wave per group, 64 probes per step over the sorted keys.
+__global__ __launch_bounds__(256) void k_group_starts(
+    const uint32_t* __restrict__ keys, int64_t n, int gshift, int64_t groups,
+    int32_t* __restrict__ starts) {
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g > groups) return;
+  const uint64_t target = (uint64_t)g << gshift;
+  // the count lies in [lo, lo + len]
+  int64_t lo = 0, len = n;
+  while (len > 64) {
+    const int64_t p = lo + (int64_t)(lane + 1) * len / 65;
+    const int c = __popcll(__ballot(keys[p] < target));
+    const int64_t p_lo = lo + (int64_t)c * len / 65;        // probe c - 1
+    const int64_t p_hi = lo + (int64_t)(c + 1) * len / 65;  // probe c
+    const int64_t nlo = c == 0 ? lo : p_lo + 1;
+    const int64_t nhi = c == 64 ? lo + len : p_hi;
+    lo = nlo;
+    len = nhi - nlo;
+  }
+  const int c =
+      __popcll(__ballot(lane < len && keys[lo + lane] < target));
+  if (lane == 0) starts[g] = (int32_t)(lo + c);
+}
+
+// first[j] = the first block of group j (blocks of per_block positions per
+// group, the last one partial), first[groups] = *count = their total.
+__global__ __launch_bounds__(1024) void k_block_prefix(
+    const int32_t* __restrict__ starts, int64_t groups, int64_t per_block,
+    int32_t* __restrict__ first, int32_t* __restrict__ count) {
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < groups; c0 += 1024) {
+    const int64_t j = c0 + threadIdx.x;
+    const uint32_t nb =
+        j < groups ? (uint32_t)((starts[j + 1] - starts[j] + per_block - 1) /
+                                per_block)
+                   : 0u;
+    uint32_t tot;
+    const uint32_t incl = block_incl_scan<1024>(nb, &tot);
+    if (j < groups) first[j] = (int32_t)(carry + incl - nb);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    first[groups] = (int32_t)carry;
+    *count = (int32_t)carry;
+  }
+}
+
+// ranges[2v], ranges[2v + 1] = the queue positions of block v: the piece
+// (v - first[j]) of group j, the last group whose first block is <= v.
+__global__ __launch_bounds__(256) void k_block_ranges(
+    const int32_t* __restrict__ starts, const int32_t* __restrict__ first,
+    int64_t groups, int64_t per_block, int64_t max_blocks,
+    int32_t* __restrict__ ranges) {
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= max_blocks || v >= first[groups]) return;
+  int64_t lo = 0, hi = groups - 1;  // at most log2(groups) + 1 steps
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  const int64_t b0 = starts[lo] + (v - first[lo]) * per_block;
+  const int64_t b1 = b0 + per_block < starts[lo + 1] ? b0 + per_block
+                                                     : starts[lo + 1];
+  ranges[2 * v] = (int32_t)b0;
+  ranges[2 * v + 1] = (int32_t)b1;
+}
+
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
+
+hipError_t launch_block_ranges(const uint32_t* keys, int64_t n, int gshift,
+                               int64_t groups, int64_t per_block, void* spare,
+                               LookupArgs* a, hipStream_t s) {
+  const int64_t max_blocks = (n + per_block - 1) / per_block + groups;
+  char* p = (char*)spare;
+  auto* starts = (int32_t*)p; p += align256((size_t)(groups + 1) * 4);
+  auto* first = (int32_t*)p;  p += align256((size_t)(groups + 1) * 4);
+  auto* count = (int32_t*)p;  p += 256;
+  auto* ranges = (int32_t*)p;
+  hipLaunchKernelGGL(k_group_starts, dim3((unsigned)((groups + 1 + 3) / 4)),
+                     dim3(256), 0, s, keys, n, gshift, groups, starts);
+  hipLaunchKernelGGL(k_block_prefix, dim3(1), dim3(1024), 0, s, starts,
+                     groups, per_block, first, count);
+  hipLaunchKernelGGL(k_block_ranges, dim3((unsigned)((max_blocks + 255) / 256)),
+                     dim3(256), 0, s, starts, first, groups, per_block,
+                     max_blocks, ranges);
+  a->blocks = ranges;
+  a->n_blocks = count;
+  a->max_blocks = max_blocks;
+  return hipGetLastError();
+}
 
 size_t sort_workspace_bytes(int64_t n, int total_bits) {
   (void)total_bits;
@@ -311,7 +410,8 @@ size_t compact_workspace_bytes(int64_t n) {
 
 hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
                        const int32_t* mat, const uint8_t* active, void* ws,
-                       const int32_t** perm_out, hipStream_t s) {
+                       const int32_t** perm_out, const uint32_t** keys_out,
+                       uint32_t** spare, hipStream_t s) {
   const int32_t nT = (int32_t)((n + kSortTile - 1) / kSortTile);
   char* p = (char*)ws;
   uint32_t* bufk[2];
@@ -344,7 +444,20 @@ hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
     else
       hipLaunchKernelGGL(k_row_scan<1024>, dim3(kRadixBins), dim3(1024), 0, s,
                          hist, nT, totals);
-    if (first && last)
+    // the last pass writes its keys only when they are asked for; the
+    // keys it reads are no longer needed after it
+    if (last && keys_out) {
+      *keys_out = bufk[dst];
+      *spare = first ? bufk[1] : bufk[cur];
+      if (first)
+        hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3(nT),
+                           dim3(kSortThreads), 0, s, src, bufk[1], nullptr,
+                           shift, hist, totals, nT, bufk[dst], bufv[dst]);
+      else
+        hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(nT),
+                           dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
+                           shift, hist, totals, nT, bufk[dst], bufv[dst]);
+    } else if (first && last)
       hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(nT),
                          dim3(kSortThreads), 0, s, src, bufk[1], nullptr, shift,
                          hist, totals, nT, bufk[dst], bufv[dst]);
