@@ -288,7 +288,7 @@ xs_status xs_lookup_batch(xs_tables_t tables, int64_t n, const double* d_E,
  *    process ends; its address is found once per device by
  *    xs_create_tables.
  *  - A sorted batch (sort != XS_SORT_NONE and n >= sort_threshold) may hold
- *    at most XS_NOALLOC_MAX_SORTED lookups (8,259,456: the paper's 1e5 to
+ *    at most XS_NOALLOC_MAX_SORTED lookups (8,323,456: the paper's 1e5 to
  *    8e6 particles in flight fit); larger sorted batches return
  *    XS_EWORKSPACE before anything is enqueued.  Unsorted batches use no
  *    scratch and take any n xs_lookup_batch takes.
@@ -297,7 +297,7 @@ xs_status xs_lookup_batch(xs_tables_t tables, int64_t n, const double* d_E,
  *    threads, or other streams not ordered after this one) race and may
  *    return wrong results.  Calls on one stream are ordered and safe. */
 #define XS_NOALLOC_SCRATCH_BYTES (128u << 20)
-#define XS_NOALLOC_MAX_SORTED 8259456
+#define XS_NOALLOC_MAX_SORTED 8323456
 xs_status xs_lookup_batch_noalloc(xs_tables_t tables, int64_t n,
                                   const double* d_E, const int32_t* d_mat,
                                   void* d_out, const xs_params* params,

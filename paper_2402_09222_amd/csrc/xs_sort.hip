@@ -17,6 +17,13 @@ namespace xs {
 
 namespace {
 
+// Radix passes take 8192 keys per block (16 per lane): with 256 digits a
+// tile then holds ~32 keys of a digit, so the scatter writes runs of ~128
+// bytes (one cache line) instead of ~64, with the same waves per compute
+// unit as 4096-key tiles (two blocks of 75 KB of LDS instead of four).
+constexpr int kRadixThreads = 512;
+constexpr int kRadixTile = kRadixThreads * kSortItems;
+
 struct SortSrc {
   const double* E;
   const int32_t* mat;
@@ -90,28 +97,29 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x,
 // (keys_out) for its scatter, which then reads 4 bytes per lookup instead of
 // the 12 of the energy and material.
 template <bool FROM_INPUT>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(
     SortSrc src, const uint32_t* __restrict__ keys_in, int shift,
     uint32_t* __restrict__ hist, int32_t nT, uint32_t* __restrict__ keys_out) {
+  static_assert(kRadixThreads >= kRadixBins, "a lane per digit");
   __shared__ uint32_t h[kRadixBins];
   const int tid = threadIdx.x;
-  h[tid] = 0;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (tid < kRadixBins) h[tid] = 0;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
   uint32_t key[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t i = base + r * kSortThreads + tid;
+    const int64_t i = base + r * kRadixThreads + tid;
     key[r] = i < src.n ? (FROM_INPUT ? src_key(src, i) : keys_in[i]) : 0u;
     if (FROM_INPUT && i < src.n) keys_out[i] = key[r];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t i = base + r * kSortThreads + tid;
+    const int64_t i = base + r * kRadixThreads + tid;
     if (i < src.n) atomicAdd(&h[(key[r] >> shift) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
-  hist[(int64_t)tid * nT + blockIdx.x] = h[tid];
+  if (tid < kRadixBins) hist[(int64_t)tid * nT + blockIdx.x] = h[tid];
 }
 
 // Row d becomes its exclusive scan over the tiles (the position of the
@@ -149,26 +157,28 @@ __global__ __launch_bounds__(NT) void k_row_scan(
 // consecutive lanes write consecutive positions of one digit's run instead
 // of 64 scattered words per wave.
 template <bool FROM_INPUT, bool WRITE_KEYS>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     SortSrc src, const uint32_t* __restrict__ keys_in,
     const uint32_t* __restrict__ vals_in, int shift,
     const uint32_t* __restrict__ offs, const uint32_t* __restrict__ totals,
     int32_t nT, uint32_t* __restrict__ keys_out,
     uint32_t* __restrict__ vals_out) {
-  constexpr int kWaves = kSortThreads / 64;
-  constexpr int kPerWave = kSortTile / kWaves;
-  static_assert(kSortThreads == kRadixBins, "one thread per digit");
+  constexpr int kWaves = kRadixThreads / 64;
+  constexpr int kPerWave = kRadixTile / kWaves;
+  static_assert(kPerWave == kSortItems * 64, "a wave's elements, 64 a round");
+  static_assert(kRadixThreads >= kRadixBins, "a lane per digit");
   __shared__ uint32_t wcnt[kWaves][kRadixBins];
   __shared__ int32_t gdelta[kRadixBins];  // output position - tile position
-  __shared__ uint32_t skey[kSortTile];
-  __shared__ uint32_t sval[kSortTile];
+  __shared__ uint32_t skey[kRadixTile];
+  __shared__ uint32_t sval[kRadixTile];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  for (int i = tid; i < kWaves * kRadixBins; i += kSortThreads)
+  const bool owner = tid < kRadixBins;  // lane tid owns digit tid
+  for (int i = tid; i < kWaves * kRadixBins; i += kRadixThreads)
     (&wcnt[0][0])[i] = 0;
-  const uint32_t tile_off = offs[(int64_t)tid * nT + blockIdx.x];
+  const uint32_t tile_off = owner ? offs[(int64_t)tid * nT + blockIdx.x] : 0u;
   __syncthreads();
 
-  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
   const int64_t base = tile0 + w * kPerWave;
   uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
@@ -187,26 +197,29 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
   __syncthreads();
   {
-    // Thread tid owns digit tid: its waves' counts become their first tile
-    // positions, and the digit's tile start maps to its output start.
+    // Lane tid < 256 owns digit tid: its waves' counts become their first
+    // tile positions, and the digit's tile start maps to its output start.
+    // The other lanes add zeros to the block's scans.
     uint32_t c[kWaves], tot = 0;
 #pragma unroll
     for (int ww = 0; ww < kWaves; ++ww) {
-      c[ww] = wcnt[ww][tid];
+      c[ww] = owner ? wcnt[ww][tid] : 0u;
       tot += c[ww];
     }
     uint32_t all;
-    const uint32_t start = block_incl_scan<kSortThreads>(tot, &all) - tot;
-    uint32_t s = start;
+    const uint32_t start = block_incl_scan<kRadixThreads>(tot, &all) - tot;
+    if (owner) {
+      uint32_t s = start;
 #pragma unroll
-    for (int ww = 0; ww < kWaves; ++ww) {
-      wcnt[ww][tid] = s;
-      s += c[ww];
+      for (int ww = 0; ww < kWaves; ++ww) {
+        wcnt[ww][tid] = s;
+        s += c[ww];
+      }
     }
     // the digit's first output position: the keys of all smaller digits
-    const uint32_t td = totals[tid];
-    const uint32_t dstart = block_incl_scan<kSortThreads>(td, &all) - td;
-    gdelta[tid] = (int32_t)((int64_t)dstart + tile_off - start);
+    const uint32_t td = owner ? totals[tid] : 0u;
+    const uint32_t dstart = block_incl_scan<kRadixThreads>(td, &all) - td;
+    if (owner) gdelta[tid] = (int32_t)((int64_t)dstart + tile_off - start);
   }
   __syncthreads();
 #pragma unroll
@@ -220,8 +233,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
   }
   __syncthreads();
-  const int cnt = (int)min<int64_t>(kSortTile, src.n - tile0);
-  for (int j = tid; j < cnt; j += kSortThreads) {
+  const int cnt = (int)min<int64_t>(kRadixTile, src.n - tile0);
+  for (int j = tid; j < cnt; j += kRadixThreads) {
     const uint32_t k = skey[j];
     const uint32_t d = (k >> shift) & (kRadixBins - 1);
     const int64_t pos = (int64_t)j + gdelta[d];
@@ -398,7 +411,7 @@ hipError_t launch_block_ranges(const uint32_t* keys, int64_t n, int gshift,
 
 size_t sort_workspace_bytes(int64_t n, int total_bits) {
   (void)total_bits;
-  const int64_t nT = (n + kSortTile - 1) / kSortTile;
+  const int64_t nT = (n + kRadixTile - 1) / kRadixTile;
   return 4 * align256((size_t)n * 4) + align256((size_t)nT * kRadixBins * 4) +
          align256(kRadixBins * 4);
 }
@@ -412,7 +425,7 @@ hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
                        const int32_t* mat, const uint8_t* active, void* ws,
                        const int32_t** perm_out, const uint32_t** keys_out,
                        uint32_t** spare, hipStream_t s) {
-  const int32_t nT = (int32_t)((n + kSortTile - 1) / kSortTile);
+  const int32_t nT = (int32_t)((n + kRadixTile - 1) / kRadixTile);
   char* p = (char*)ws;
   uint32_t* bufk[2];
   uint32_t* bufv[2];
@@ -433,10 +446,10 @@ hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
     // The first pass writes the keys to bufk[1], which the second pass
     // rewrites only after the first pass's scatter has read them.
     if (first)
-      hipLaunchKernelGGL((k_radix_hist<true>), dim3(nT), dim3(kSortThreads), 0,
+      hipLaunchKernelGGL((k_radix_hist<true>), dim3(nT), dim3(kRadixThreads), 0,
                          s, src, nullptr, shift, hist, nT, bufk[1]);
     else
-      hipLaunchKernelGGL((k_radix_hist<false>), dim3(nT), dim3(kSortThreads), 0,
+      hipLaunchKernelGGL((k_radix_hist<false>), dim3(nT), dim3(kRadixThreads), 0,
                          s, src, bufk[cur], shift, hist, nT, nullptr);
     if (nT <= 512)
       hipLaunchKernelGGL(k_row_scan<256>, dim3(kRadixBins), dim3(256), 0, s,
@@ -451,27 +464,27 @@ hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
       *spare = first ? bufk[1] : bufk[cur];
       if (first)
         hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3(nT),
-                           dim3(kSortThreads), 0, s, src, bufk[1], nullptr,
+                           dim3(kRadixThreads), 0, s, src, bufk[1], nullptr,
                            shift, hist, totals, nT, bufk[dst], bufv[dst]);
       else
         hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(nT),
-                           dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
+                           dim3(kRadixThreads), 0, s, src, bufk[cur], bufv[cur],
                            shift, hist, totals, nT, bufk[dst], bufv[dst]);
     } else if (first && last)
       hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(nT),
-                         dim3(kSortThreads), 0, s, src, bufk[1], nullptr, shift,
+                         dim3(kRadixThreads), 0, s, src, bufk[1], nullptr, shift,
                          hist, totals, nT, bufk[dst], bufv[dst]);
     else if (first)
       hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3(nT),
-                         dim3(kSortThreads), 0, s, src, bufk[1], nullptr, shift,
+                         dim3(kRadixThreads), 0, s, src, bufk[1], nullptr, shift,
                          hist, totals, nT, bufk[dst], bufv[dst]);
     else if (last)
       hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(nT),
-                         dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
+                         dim3(kRadixThreads), 0, s, src, bufk[cur], bufv[cur],
                          shift, hist, totals, nT, bufk[dst], bufv[dst]);
     else
       hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(nT),
-                         dim3(kSortThreads), 0, s, src, bufk[cur], bufv[cur],
+                         dim3(kRadixThreads), 0, s, src, bufk[cur], bufv[cur],
                          shift, hist, totals, nT, bufk[dst], bufv[dst]);
     cur = dst;
   }

@@ -29,7 +29,7 @@ XS_BUILD_UNION_BY_MATERIAL = 8
 XS_BUILD_FP32_PAIRS = 16
 XS_MAX_HASH_GRIDS = 8
 XS_NOALLOC_SCRATCH_BYTES = 128 << 20
-XS_NOALLOC_MAX_SORTED = 8259456
+XS_NOALLOC_MAX_SORTED = 8323456
 INT64_MAX = (1 << 63) - 1
 
 GRIDS = {"nuclide": XS_GRID_NUCLIDE, "hash": XS_GRID_HASH,

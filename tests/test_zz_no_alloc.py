@@ -84,7 +84,7 @@ def test_noalloc_empty_and_limit(env):
     with pytest.raises(xs.XsError) as ei:
         xs.xs_lookup_batch_noalloc(env["h"], E, m, params=p)
     assert ei.value.status == xs.XS_EWORKSPACE
-    assert "at most 8259456 sorted lookups" in str(ei.value)
+    assert "at most 8323456 sorted lookups" in str(ei.value)
     # The largest sorted batch fills the scratch exactly and still matches
     # xs_lookup_batch.
     n = xs.XS_NOALLOC_MAX_SORTED
