@@ -787,13 +787,17 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
   __shared__ int64_t s_row[2];
   __shared__ double s_red[2][16];
   const int tid = threadIdx.x;
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t first, end;  // this block's queue positions: first .. end - 1
+  int64_t blk, first, end;  // this block's queue positions: first .. end - 1
   if (a.blocks) {
-    if (blk >= *a.n_blocks) return;  // the whole block leaves
+    // The grid is sized for the most ranges a queue can have; the ranges
+    // actually cut are dealt evenly over the XCDs and the rest leave.
+    const int64_t nr = *a.n_blocks;
+    if ((int64_t)blockIdx.x >= nr) return;  // the whole block leaves
+    blk = xcd_remap(blockIdx.x, nr);
     first = a.blocks[2 * blk];
     end = a.blocks[2 * blk + 1];
   } else {
+    blk = xcd_remap(blockIdx.x, gridDim.x);
     first = blk * (int64_t)blockDim.x * LPT;
     end = a.count_dev ? *a.count_dev : a.n;
   }
