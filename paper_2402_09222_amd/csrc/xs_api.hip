@@ -537,12 +537,18 @@ xs_status lookup_common(xs_tables_t h, int64_t n, const double* E,
                      p.sort != XS_SORT_ENERGY && n >= 4096 &&
                      group_bits < 31 &&
                      ((int64_t)1 << group_bits) <= std::max<int64_t>(1, nb / 4);
+    // With a mask the inactive lookups sort last (the key's top bit): the
+    // kernels serve only the active head of the queue, as blocks cut from
+    // the groups without the flag or as a device-side count.
     const uint32_t* keys = nullptr;
     uint32_t* spare = nullptr;
+    const int64_t groups = (int64_t)1 << group_bits;
     XS_HIP(launch_sort(key, n, E, mat, masked ? active : nullptr, ws, &a.perm,
-                       cut ? &keys : nullptr, &spare, s));
+                       cut ? &keys : nullptr, &spare,
+                       masked && !cut ? &a.count_dev : nullptr, s));
     if (cut)
-      XS_HIP(launch_block_ranges(keys, n, rest, (int64_t)1 << group_bits,
+      XS_HIP(launch_block_ranges(keys, n, rest, groups,
+                                 key.flag_bit ? groups >> 1 : groups,
                                  per_block, spare, &a, s));
   } else if (compact) {
     XS_HIP(launch_compact(n, active, ws, &a.perm, &a.count_dev, s));

@@ -213,7 +213,9 @@ hipError_t launch_union_index_by_material(const DevTables& t, int32_t Ltot,
                                           int32_t* uidx, hipStream_t s);
 
 // Lookup kernels (xs_lookup_*.hip).  count_dev, when not null, holds the
-// number of valid entries of perm (device-side queue length).
+// number of valid entries of perm (device-side queue length); the kernels
+// then deal the blocks that hold queue entries evenly over the XCDs and the
+// rest of the grid (sized for n) leaves at once.
 struct LookupArgs {
   int64_t n;
   const double* E;
@@ -253,20 +255,25 @@ size_t compact_workspace_bytes(int64_t n);
 // Sorts lookups by `key`; on return *perm_out points into ws at the
 // permutation (sorted position -> input index).  With keys_out, the sorted
 // keys are written too (*keys_out), and *spare points at n words of ws the
-// sort no longer needs.
+// sort no longer needs.  With active_out and a key with the inactive flag,
+// *active_out points into ws at the number of active lookups (device
+// int64), which lead the sorted order.
 hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
                        const int32_t* mat, const uint8_t* active, void* ws,
                        const int32_t** perm_out, const uint32_t** keys_out,
-                       uint32_t** spare, hipStream_t s);
+                       uint32_t** spare, const int64_t** active_out,
+                       hipStream_t s);
 // Block ranges of the LDS-staged kernel over sorted keys: the queue is cut
 // at every change of key >> gshift (groups of one material) and each group
 // into pieces of per_block positions.  groups = the number of possible
-// values of key >> gshift; the ranges, their count and the starts use
-// 8 * (2 * groups + 2 + n / per_block) + 256 bytes of `spare`.  Sets
-// a->blocks, a->n_blocks and a->max_blocks (an upper bound of the count).
+// values of key >> gshift; only the ranges of groups [0, used) are served
+// (used = groups / 2 when the top group bit is the inactive flag).  The
+// ranges and the starts use 8 * (2 * groups + 2 + n / per_block) + 256
+// bytes of `spare`.  Sets a->blocks, a->n_blocks and a->max_blocks (an
+// upper bound of the count).
 hipError_t launch_block_ranges(const uint32_t* keys, int64_t n, int gshift,
-                               int64_t groups, int64_t per_block, void* spare,
-                               LookupArgs* a, hipStream_t s);
+                               int64_t groups, int64_t used, int64_t per_block,
+                               void* spare, LookupArgs* a, hipStream_t s);
 // Stable compaction of active slots: perm (in ws) lists them in input
 // order, *count_out (device) their number.
 hipError_t launch_compact(int64_t n, const uint8_t* active, void* ws,

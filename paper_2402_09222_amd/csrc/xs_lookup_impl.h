@@ -87,6 +87,22 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   return x * q + (x < r ? x : r) + s;
 }
 
+// This block's index among the blocks that hold queue positions, remapped as
+// above, or -1 when it holds none.  With a device-side queue length (a
+// compacted queue, or the active head of a sorted one) the grid is sized
+// for the whole batch: only the first ceil(count / per_block) blocks have
+// work, and remapping over those (not the grid) spreads them over all XCDs.
+__device__ __forceinline__ int64_t queue_block(const LookupArgs& a,
+                                               int64_t per_block) {
+  int64_t nb = gridDim.x;
+  if (a.count_dev) {
+    const int64_t c = (*a.count_dev + per_block - 1) / per_block;
+    nb = c < nb ? c : nb;
+  }
+  if ((int64_t)blockIdx.x >= nb) return -1;
+  return xcd_remap(blockIdx.x, nb);
+}
+
 // Largest block for LPT lookups per lane with U nuclides in flight: more
 // independent chains per lane need more registers, so fewer lanes fit per
 // compute unit.
@@ -617,9 +633,11 @@ __device__ __forceinline__ void walk_material(const DevTables& t, int mat,
 template <int GRID, int PREC, int LPT, int U>
 __global__ __launch_bounds__(max_block_for(LPT, U)) void k_lookup(
     const DevTables t, const LookupArgs a) {
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t per_block = (int64_t)blockDim.x * LPT;
+  const int64_t blk = queue_block(a, per_block);
+  if (blk < 0) return;
   const int64_t n = a.count_dev ? *a.count_dev : a.n;
-  const int64_t first = blk * (int64_t)blockDim.x * LPT + threadIdx.x;
+  const int64_t first = blk * per_block + threadIdx.x;
 
   double e[LPT];
   int m[LPT];
@@ -797,7 +815,8 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
     first = a.blocks[2 * blk];
     end = a.blocks[2 * blk + 1];
   } else {
-    blk = xcd_remap(blockIdx.x, gridDim.x);
+    blk = queue_block(a, (int64_t)blockDim.x * LPT);
+    if (blk < 0) return;  // the whole block leaves
     first = blk * (int64_t)blockDim.x * LPT;
     end = a.count_dev ? *a.count_dev : a.n;
   }
@@ -1051,7 +1070,9 @@ __global__ __launch_bounds__(kWaveBlock) void k_lookup_wave(const DevTables t,
   __shared__ T terms[kWaveBlock / 64][64][XS_CHANNELS];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t n = a.count_dev ? *a.count_dev : a.n;
-  const int64_t q = xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + w;
+  const int64_t blk = queue_block(a, blockDim.x >> 6);
+  if (blk < 0) return;
+  const int64_t q = blk * (blockDim.x >> 6) + w;
   if (q >= n) return;
   const int64_t o = a.perm ? (int64_t)a.perm[q] : q;
   if ((uint64_t)o >= (uint64_t)a.n) return;

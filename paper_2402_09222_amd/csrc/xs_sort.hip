@@ -306,6 +306,17 @@ __global__ __launch_bounds__(kSortThreads) void k_compact_scatter(
   }
 }
 
+// The number of active lookups after a sort whose key carries the inactive
+// flag as its top bit: the keys whose last-pass digit is below the flag's.
+__global__ __launch_bounds__(kRadixBins) void k_count_below(
+    const uint32_t* __restrict__ totals, uint32_t flag_digit,
+    int64_t* __restrict__ count) {
+  uint32_t all;
+  const uint32_t x = threadIdx.x < flag_digit ? totals[threadIdx.x] : 0u;
+  (void)block_incl_scan<kRadixBins>(x, &all);
+  if (threadIdx.x == 0) *count = all;
+}
+
 // ---- block ranges over a sorted queue -------------------------------------
 //
 // The LDS-staged lookup shares one material's windows across a block, so a
@@ -341,10 +352,10 @@ __global__ __launch_bounds__(256) void k_group_starts(
 }
 
 // first[j] = the first block of group j (blocks of per_block positions per
-// group, the last one partial), first[groups] = *count = their total.
+// group, the last one partial), first[groups] = their total.
 __global__ __launch_bounds__(1024) void k_block_prefix(
     const int32_t* __restrict__ starts, int64_t groups, int64_t per_block,
-    int32_t* __restrict__ first, int32_t* __restrict__ count) {
+    int32_t* __restrict__ first) {
   uint32_t carry = 0;
   for (int64_t c0 = 0; c0 < groups; c0 += 1024) {
     const int64_t j = c0 + threadIdx.x;
@@ -357,20 +368,18 @@ __global__ __launch_bounds__(1024) void k_block_prefix(
     if (j < groups) first[j] = (int32_t)(carry + incl - nb);
     carry += tot;
   }
-  if (threadIdx.x == 0) {
-    first[groups] = (int32_t)carry;
-    *count = (int32_t)carry;
-  }
+  if (threadIdx.x == 0) first[groups] = (int32_t)carry;
 }
 
 // ranges[2v], ranges[2v + 1] = the queue positions of block v: the piece
-// (v - first[j]) of group j, the last group whose first block is <= v.
+// (v - first[j]) of group j, the last group whose first block is <= v, for
+// the blocks of groups [0, used).
 __global__ __launch_bounds__(256) void k_block_ranges(
     const int32_t* __restrict__ starts, const int32_t* __restrict__ first,
-    int64_t groups, int64_t per_block, int64_t max_blocks,
+    int64_t groups, int64_t used, int64_t per_block, int64_t max_blocks,
     int32_t* __restrict__ ranges) {
   const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= max_blocks || v >= first[groups]) return;
+  if (v >= max_blocks || v >= first[used]) return;
   int64_t lo = 0, hi = groups - 1;  // at most log2(groups) + 1 steps
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) >> 1;
@@ -388,23 +397,23 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
 hipError_t launch_block_ranges(const uint32_t* keys, int64_t n, int gshift,
-                               int64_t groups, int64_t per_block, void* spare,
-                               LookupArgs* a, hipStream_t s) {
-  const int64_t max_blocks = (n + per_block - 1) / per_block + groups;
+                               int64_t groups, int64_t used, int64_t per_block,
+                               void* spare, LookupArgs* a, hipStream_t s) {
+  const int64_t max_blocks = (n + per_block - 1) / per_block + used;
   char* p = (char*)spare;
   auto* starts = (int32_t*)p; p += align256((size_t)(groups + 1) * 4);
   auto* first = (int32_t*)p;  p += align256((size_t)(groups + 1) * 4);
-  auto* count = (int32_t*)p;  p += 256;
+  p += 256;
   auto* ranges = (int32_t*)p;
   hipLaunchKernelGGL(k_group_starts, dim3((unsigned)((groups + 1 + 3) / 4)),
                      dim3(256), 0, s, keys, n, gshift, groups, starts);
   hipLaunchKernelGGL(k_block_prefix, dim3(1), dim3(1024), 0, s, starts,
-                     groups, per_block, first, count);
+                     groups, per_block, first);
   hipLaunchKernelGGL(k_block_ranges, dim3((unsigned)((max_blocks + 255) / 256)),
-                     dim3(256), 0, s, starts, first, groups, per_block,
+                     dim3(256), 0, s, starts, first, groups, used, per_block,
                      max_blocks, ranges);
   a->blocks = ranges;
-  a->n_blocks = count;
+  a->n_blocks = first + used;  // the blocks of the served groups
   a->max_blocks = max_blocks;
   return hipGetLastError();
 }
@@ -424,7 +433,8 @@ size_t compact_workspace_bytes(int64_t n) {
 hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
                        const int32_t* mat, const uint8_t* active, void* ws,
                        const int32_t** perm_out, const uint32_t** keys_out,
-                       uint32_t** spare, hipStream_t s) {
+                       uint32_t** spare, const int64_t** active_out,
+                       hipStream_t s) {
   const int32_t nT = (int32_t)((n + kRadixTile - 1) / kRadixTile);
   char* p = (char*)ws;
   uint32_t* bufk[2];
@@ -489,6 +499,16 @@ hipError_t launch_sort(const SortKey& key, int64_t n, const double* E,
     cur = dst;
   }
   *perm_out = (const int32_t*)bufv[cur];
+  if (active_out && key.flag_bit) {
+    // the flag is the key's top bit, in the last pass's digit; the count
+    // goes where the histograms were (no longer read)
+    const int last_shift = (passes - 1) * kRadixBits;
+    const uint32_t flag_digit = 1u << (key.total_bits - 1 - last_shift);
+    auto* count = (int64_t*)hist;
+    hipLaunchKernelGGL(k_count_below, dim3(1), dim3(kRadixBins), 0, s, totals,
+                       flag_digit, count);
+    *active_out = count;
+  }
   return hipGetLastError();
 }
 

@@ -322,17 +322,26 @@ def test_union_bin_edges(cfg1):
 
 @pytest.mark.parametrize("queue", [xs.XS_QUEUE_COMPACT, xs.XS_QUEUE_PREDICATED])
 @pytest.mark.parametrize("sort", ["none", "material_energy", "band_material"])
-def test_active_mask(cfg1, queue, sort):
-    """Inactive slots keep their sentinel; active ones match the oracle."""
+@pytest.mark.parametrize("frac", [0.3, 0.0, 1.0])
+def test_active_mask(cfg1, queue, sort, frac):
+    """Inactive slots keep their sentinel; active ones match the oracle.
+    A compacted queue, or a sorted one whose inactive lookups go last,
+    serves only its active head (a device-side count, or block ranges of
+    the groups without the inactive flag): none, some or all active, in
+    the per-lane, LDS-staged and one-wave-per-lookup kernels."""
     n = len(cfg1["q"])
     s = synth.Stream(33, 1)
-    act = (s.uniform(n) < 0.3).astype(np.uint8)
+    act = (s.uniform(n) < frac).astype(np.uint8)
     sentinel = -7.25
     for prec, ref in ((xs.XS_FP64, cfg1["ref"]), (xs.XS_FP32, cfg1["ref32"])):
         dt = torch.float64 if prec == xs.XS_FP64 else torch.float32
         for shape in (dict(lookups_per_thread=2),
                       dict(grid="unionized", lookups_per_thread=1, unroll=1,
-                           lds_stage=1, block_size=128)):
+                           lds_stage=1, block_size=128),
+                      dict(grid="unionized", lookups_per_thread=1, unroll=1,
+                           lds_stage=3, block_size=64),
+                      dict(grid="unionized", lookups_per_thread=1, unroll=1,
+                           wave_per_lookup=1, block_size=128)):
             out = torch.full((n, 5), sentinel, dtype=dt, device="cuda:0")
             p = xs.make_params(precision=prec, sort=sort, sort_threshold=0,
                                queue=queue, **shape)
