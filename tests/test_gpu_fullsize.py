@@ -6,7 +6,8 @@ the host's cores); the GPU outputs are compared with it element by element:
 the plain FP64 lookup and the benchmark's tuned path (unionized grid indexed
 by material, banded sort, LDS staging in each stage shape at 128 and 256
 lanes) over the whole batch, and the brackets of every (lookup, nuclide)
-pair of the batch for all three grid methods, in 1M-lookup chunks.  Other
+pair of the batch for all three grid methods, in 1M-lookup chunks, and
+half-active masked batches (compacted, sorted and predicated).  Other
 launch shapes are checked through properties that hold at any size: every
 grid method, sort policy and launch shape gives bit-identical sums within
 one precision.
@@ -113,6 +114,44 @@ def test_tuned_path_whole_batch(full, shape):
     rel = np.abs(out.astype(np.float64) - ref) / ref
     say("  max rel per channel", rel.max(axis=0), "mean", rel.mean(axis=0))
     assert rel.max() <= 2e-6
+
+
+# Masked batches at full size: half of the slots active.  A compacted queue,
+# or a sorted one whose inactive lookups go last, is served through its
+# active head (device-side count, or block ranges of the unflagged groups)
+# dealt over all XCDs.
+MASKED_SHAPES = [dict(lds_stage=1, block_size=128, sort="band_material",
+                      queue=xs.XS_QUEUE_COMPACT),
+                 dict(lds_stage=3, block_size=128, sort="band_material",
+                      queue=xs.XS_QUEUE_COMPACT),
+                 dict(lds_stage=1, block_size=128, sort="none",
+                      queue=xs.XS_QUEUE_COMPACT),
+                 dict(lds_stage=0, block_size=256, sort="none",
+                      queue=xs.XS_QUEUE_COMPACT),
+                 dict(lds_stage=0, block_size=256, sort="none",
+                      queue=xs.XS_QUEUE_PREDICATED)]
+
+
+@pytest.mark.parametrize("shape", MASKED_SHAPES,
+                         ids=[f"stage{k['lds_stage']}-{k['sort']}-q{k['queue']}"
+                              for k in MASKED_SHAPES])
+def test_masked_half_active_whole_batch(full, shape):
+    say("masked full size, half active", shape)
+    act = (synth.Stream(43, 1).uniform(N) < 0.5).astype(np.uint8)
+    sentinel = -3.5
+    out = torch.full((N, 5), sentinel, dtype=torch.float32, device="cuda:0")
+    p = xs.make_params(precision=xs.XS_FP32, grid="unionized",
+                       sort_threshold=0, lookups_per_thread=1, unroll=1,
+                       **shape)
+    xs.xs_lookup_active(full["h"], full["E"], full["m"],
+                        torch.from_numpy(act).to("cuda:0"), out, params=p)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    a = act.astype(bool)
+    assert np.all(o[~a] == sentinel), shape
+    bad = np.count_nonzero(o[a].view(np.uint32) !=
+                           full["ref32_all"][a].view(np.uint32))
+    assert bad == 0, (shape, bad)
 
 
 @pytest.mark.parametrize("grid", ["nuclide", "hash", "unionized"])
