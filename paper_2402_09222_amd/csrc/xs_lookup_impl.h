@@ -42,9 +42,9 @@ __device__ __forceinline__ int bisect_le(const double* __restrict__ g, int n,
 // range into 65 parts, and the count of probes <= e (a prefix, the array
 // being sorted) names the part that holds the answer.  The range shrinks 65
 // times per step: 4 dependent loads for the 4M-point union grid instead of
-// 22, for 64 cache lines per step instead of one, so it pays where few
-// waves search (the block edges of the LDS-staged kernel: 3 % faster at 10M
-// lookups).  Every lane of the wave must call it with the same arguments.
+// 22, for 64 cache lines per step instead of one.  It is the fallback of
+// wave_union_row below, which reads one logarithmic bin's points instead.
+// Every lane of the wave must call it with the same arguments.
 __device__ __forceinline__ int wave_bisect_le(const double* __restrict__ g,
                                               int n, double e, int lane) {
   int lo = 0, len = n;  // answer in [lo, lo + len); g[lo] <= e unless lo == 0
@@ -918,13 +918,16 @@ __global__ __launch_bounds__(1024 / LPT) void k_lookup_lds(const DevTables t,
     hi_e = fmax(hi_e, s_red[1][i]);
   }
 
-  // Search state of the two edge energies: the union grid is bisected once
-  // by two lanes; the hash bin is arithmetic; bisection keeps no state.
+  // Search state of the two edge energies: the union grid is searched once
+  // per edge by a whole wave (the edge's logarithmic bin read in one round,
+  // two dependent loads; measured against a 64-way search of the whole grid,
+  // four: 2-3 % faster from 1e6 to 1e7 lookups); the hash bin is
+  // arithmetic; bisection keeps no state.
   Locator<GRID> edge_lo, edge_hi;
   if constexpr (GRID == XS_GRID_UNIONIZED) {
     // waves 0 and 1 (or wave 0 twice in a one-wave block)
     for (int k = w; k < 2; k += nw) {
-      const int row = wave_bisect_le(t.u, (int)t.U, k == 0 ? lo_e : hi_e, lane);
+      const int row = wave_union_row(t, k == 0 ? lo_e : hi_e, lane);
       if (lane == 0) s_row[k] = row;
     }
     __syncthreads();
